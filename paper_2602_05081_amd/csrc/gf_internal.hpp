@@ -1,0 +1,194 @@
+// Internal definitions of the Gabor-field HIP library (gfx950).
+//
+// Device data layout of a resident scene (all in HBM, Morton order):
+//   prims  : n x 64 B records (4 x float4), read wave-uniformly through the
+//            scalar cache by the packet traversal:
+//            [mu.x mu.y mu.z phi] [A00 A01 A02 A11] [A12 A22 f.x f.y]
+//            [f.z amp cell orig]  with A = Sigma^-1 (float32), amp = rho alpha /
+//            (4 pi s0 s1 s2), cell = 3 level + bin, orig = caller index.
+//   nodes  : (n-1) x 64 B traversal records of the internal LBVH nodes, each
+//            holding both child boxes so one scalar load tests both children:
+//            [lbox lo/hi] [rbox lo/hi] [lchild rchild cells pad]; a child id
+//            c >= 0 is an internal node, c < 0 is the leaf (Morton index) ~c.
+//   grid   : G^3 voxels x 12 cells of float32 majorants over the root box.
+//   canon  : the canonical LBVH arrays (keys, perm, left, right, parent,
+//            aabb, cellor) kept for export and refit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gaborfields.h"
+
+#define GF_NCELLS 12
+#define GF_STACK 128
+
+struct TNode {
+    float lbox[6];
+    float rbox[6];
+    int lchild, rchild;
+    uint32_t cells;  // low 16 bits: left subtree cells, high 16 bits: right
+    int pad;
+};
+static_assert(sizeof(TNode) == 64, "traversal node must be 64 bytes");
+
+// Scene as seen by kernels (passed by value).
+struct SceneView {
+    const float4* __restrict__ prims;
+    const TNode* __restrict__ nodes;
+    const float* __restrict__ grid;
+    const float4* __restrict__ aux;
+    int n;
+    float r, r2;
+    int G;
+    float glo[3], ghi[3], ginv[3];  // grid box and voxels per unit length
+    float med[GF_NCELLS];           // per-cell median |k_W|
+};
+
+struct MaskView {
+    uint32_t cells;                          // 12 used bits
+    const uint32_t* __restrict__ prim_bits;  // caller order, may be null
+};
+
+struct gf_scene_s {
+    int device;
+    int64_t n;
+    float rho, r;
+    int G;
+    int depth;  // largest number of internal nodes on a root-to-leaf path
+    double fmax2;
+    float lo[3], hi[3];
+    uint64_t nonempty;
+    int64_t cell_count[GF_NCELLS];
+    float med[GF_NCELLS];
+    // device memory
+    float4* prims;
+    float4* aux;  // adjoint data, 3 x float4 per primitive (Morton order):
+                  // [qhat w x y z] [|q| s0 s1 s2] [alpha, rho/(4 pi s0 s1 s2), 0, 0]
+    TNode* nodes;
+    float* grid;
+    uint64_t* keys;
+    int32_t* perm;
+    int32_t* left;
+    int32_t* right;
+    int32_t* parent;
+    float* aabb;
+    uint64_t* cellor;
+    size_t bytes;
+};
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+gf_status gf_fail(gf_status st, const char* fmt, ...);
+gf_status gf_hip_check(hipError_t e, const char* what);
+#define GF_HIP(call)                                               \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return gf_hip_check(_e, #call);      \
+    } while (0)
+
+// Weideman coefficients live in constant memory of every translation unit
+// that evaluates w(z); gf_ensure_weideman() uploads them once per device.
+gf_status gf_ensure_weideman_tau();
+gf_status gf_ensure_weideman_grad();
+
+SceneView gf_scene_view(const gf_scene_s* s);
+unsigned gf_packet_blocks(int64_t n, int tile_w);
+gf_status gf_check_rays(int64_t n, int tile_w, const char* who);
+MaskView gf_mask_view(const gf_mask& m);
+gf_status gf_check_mask(const gf_scene_s* s, const gf_mask& m);
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+#define GF_PI 3.14159265358979323846
+#define GF_INV_2PI 0.15915494309189533577
+
+static __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+static __device__ __forceinline__ uint64_t lanemask_lt() {
+    int l = __lane_id();
+    return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+static __device__ __forceinline__ int uniform_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// fractional part in [-0.5, 0.5] of a phase given in cycles (binary64)
+static __device__ __forceinline__ float frac_cycles(double c) { return (float)(c - rint(c)); }
+
+// sin / cos of 2 pi x for |x| <= 0.5
+static __device__ __forceinline__ void sincos2pi(float x, float* s, float* c) { sincospif(2.0f * x, s, c); }
+
+// Philox4x32-10 (Salmon et al., SC 2011): 10 rounds of two 32x32->64
+// multiplications with Weyl-sequence key bumps.
+static __device__ __forceinline__ uint4 philox4x32(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Counter-based stream: key = seed, counter = (a, b, block, tag).
+struct Rng {
+    uint32_t k0, k1, a, b, tag, blk;
+    uint4 buf;
+    int used;
+    __device__ void init(uint64_t seed, uint32_t a_, uint32_t b_, uint32_t tag_) {
+        k0 = (uint32_t)seed;
+        k1 = (uint32_t)(seed >> 32);
+        a = a_;
+        b = b_;
+        tag = tag_;
+        blk = 0;
+        used = 4;
+    }
+    // uniform in (0, 1): ((x >> 8) + 0.5) 2^-24
+    __device__ float u() {
+        if (used == 4) {
+            buf = philox4x32(make_uint4(a, b, blk, tag), k0, k1);
+            ++blk;
+            used = 0;
+        }
+        uint32_t x = used == 0 ? buf.x : used == 1 ? buf.y : used == 2 ? buf.z : buf.w;
+        ++used;
+        return ((float)(x >> 8) + 0.5f) * (1.0f / 16777216.0f);
+    }
+};
+
+static __device__ __forceinline__ bool mask_keep(const MaskView& m, int cell, int orig) {
+    if (!((m.cells >> cell) & 1u)) return false;
+    if (m.prim_bits && !((m.prim_bits[orig >> 5] >> (orig & 31)) & 1u)) return false;
+    return true;
+}
+
+// Robust slab test of a ray against a box (conservative: the far distance is
+// inflated by a few ulps so that rounding never rejects a grazing chord).
+static __device__ __forceinline__ bool slab_hit(const float* b, float ox, float oy, float oz, float ix, float iy,
+                                                float iz, float tmin, float tmax) {
+    float t0x = (b[0] - ox) * ix, t1x = (b[3] - ox) * ix;
+    float t0y = (b[1] - oy) * iy, t1y = (b[4] - oy) * iy;
+    float t0z = (b[2] - oz) * iz, t1z = (b[5] - oz) * iz;
+    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    return tn <= tf + fabsf(tf) * 1e-6f + 1e-30f;
+}
+
+static __device__ __forceinline__ bool box_contains(const float* b, float x, float y, float z) {
+    return x >= b[0] && x <= b[3] && y >= b[1] && y <= b[4] && z >= b[2] && z <= b[5];
+}
+
+// Majorant of |kappa| in the voxel holding grid index (ix, iy, iz) for a set of
+// per-cell weights.
+static __device__ __forceinline__ float voxel_majorant(const SceneView& S, int vox, const float* cw) {
+    const float* g = S.grid + (size_t)vox * GF_NCELLS;
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < GF_NCELLS; ++c) acc += cw[c] * g[c];
+    return acc;
+}
