@@ -41,9 +41,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="blob100k")
     ap.add_argument("--spp", type=int, default=8)
+    ap.add_argument("--render", action="store_true", help="include the single-scattering render in every step")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -60,6 +63,13 @@ def main():
     from gen import workloads as W
 
     torch.cuda.init()
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     name = args.workload
     params_h, rays_h, rho = W.scene(name), W.rays(name), W.rho(name)
     width = int(math.isqrt(rays_h.shape[0]))
@@ -93,10 +103,11 @@ def main():
             a.record()
             gf.gf_optical_depth(scene, rays, m, image_width=width)
             b.record()
-            gf.gf_render(scene, rays, desc(m), image_width=width, want_var=False)
+            if args.render:
+                gf.gf_render(scene, rays, desc(m), image_width=width, want_var=False)
             c.record()
             evs.append((a, b, c))
-        if record:
+        if record is not None:
             record.append((e0, e1, evs))
         return scene, bits
 
@@ -119,7 +130,8 @@ def main():
             timings["render"][k].append(b.elapsed_time(c))
     tau_ms = [float(np.mean(t)) for t in timings["tau"]]
     ren_ms = [float(np.mean(t)) for t in timings["render"]]
-    units = 4 * npix * (1 + args.spp)
+    spp_r = args.spp if args.render else 0
+    units = 4 * npix * (1 + spp_r)
     value = units / (ms_per_step * 1e-3) / 1e6
 
     # algorithmic work of the timed launches (same inputs and seeds)
@@ -130,31 +142,36 @@ def main():
         nodes, hits = gf.gf_optical_depth_counts(scene, rays, m, image_width=width)
         nn, nh = int(nodes.sum().item()), int(hits.sum().item())
         tau_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + PRIM_BYTES * nh + NODE_BYTES * nn)
-        tent, qn, qp, vox = gf.gf_render_counts(scene, rays, desc(m), image_width=width)
-        ren_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + NODE_BYTES * qn + PRIM_BYTES * qp + VOXEL_BYTES * vox)
+        if args.render:
+            tent, qn, qp, vox = gf.gf_render_counts(scene, rays, desc(m), image_width=width)
+            ren_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + NODE_BYTES * qn + PRIM_BYTES * qp + VOXEL_BYTES * vox)
+        else:
+            ren_bytes.append(0)
     torch.cuda.synchronize()
     tau_gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(tau_bytes, tau_ms)]
-    ren_gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(ren_bytes, ren_ms)]
-    dominant = "render" if sum(ren_ms) >= sum(tau_ms) else "optical_depth"
+    ren_gbs = [b / (t * 1e-3) / 1e9 if t > 0 else 0.0 for b, t in zip(ren_bytes, ren_ms)]
+    dominant = "render" if args.render and sum(ren_ms) >= sum(tau_ms) else "optical_depth"
     if dominant == "render":
         ach = sum(ren_bytes) / (sum(ren_ms) * 1e-3) / 1e9
     else:
         ach = sum(tau_bytes) / (sum(tau_ms) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dominant}
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, dominant),
+                "kernel": dominant}
 
     result = {
         "metric": "Mrays/s transmittance at full & masked LOD; p50/p99 render-request latency",
         "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (f64 geometry setup)", "data": "synthetic",
-        "config": {"workload": "%s: %d Gabors (64-blob field), %dx%d pinhole, masks %s, %d-spp single scattering"
-                   % (name, params.shape[0], width, width, "/".join(mask_names), args.spp),
+        "config": {"workload": "%s: %d Gabors (64-blob field), %dx%d pinhole, masks %s%s"
+                   % (name, params.shape[0], width, width, "/".join(mask_names),
+                      ", %d-spp single scattering" % args.spp if args.render else ", optical depth and transmittance"),
                    "global_batch": npix, "parallelism": "single GPU"},
         "roofline": roofline,
         "per_mask": {mask_names[k]: {"tau_ms": round(tau_ms[k], 3), "tau_Mrays_s": round(npix / tau_ms[k] / 1e3, 1),
                                      "tau_alg_GBs": round(tau_gbs[k], 1), "render_ms": round(ren_ms[k], 3),
-                                     "render_Msamples_s": round(npix * args.spp / ren_ms[k] / 1e3, 2),
+                                     "render_Msamples_s": round(npix * spp_r / max(ren_ms[k], 1e-9) / 1e3, 2),
                                      "render_alg_GBs": round(ren_gbs[k], 1)} for k in range(4)},
         "build_ms": round(float(np.mean(timings["build"])), 3),
     }
@@ -166,6 +183,26 @@ def main():
                                               ms_per_step)
     scene.close()
     print(json.dumps(result), flush=True)
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (profiles/<kernel>_<workload>_pmc.txt), scaled by the calibration
+    factors recorded there; None when no summary exists or the HIP sources
+    changed since it was taken."""
+    sys.path.insert(0, os.path.join(ROOT, "profiles"))
+    import summarize
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read().splitlines()
+    if not any(l.startswith("# source hash: %s" % summarize.source_hash()) for l in text):
+        return None
+    name = {"optical_depth": "void k_tau<false>", "render": "void k_render<false>"}[kernel]
+    for line in text:
+        if line.startswith(name):
+            return int(float(line.split()[-1]) * 1e6)
+    return None
 
 
 def serving(args, gf, W, np, torch):
@@ -203,17 +240,21 @@ def cpu_baseline(args, np, params, rays, rho, tau_ms, ren_ms, npix, units, ms_pe
     t0 = time.perf_counter()
     oracle.tau(params, rays[sub], rho=rho)
     t_tau = (time.perf_counter() - t0) / len(sub)
+    spp_r = args.spp if args.render else 0
     sub_r = W.pixel_subset(rays.shape[0], k=16, seed=6)
-    t0 = time.perf_counter()
-    oracle.render(params, rays[sub_r], args.spp, seed=3, rho=rho, multiple=False, albedo=0.9)
-    t_ren = (time.perf_counter() - t0) / (len(sub_r) * args.spp)
+    t_ren = 0.0
+    if spp_r:
+        t0 = time.perf_counter()
+        oracle.render(params, rays[sub_r], args.spp, seed=3, rho=rho, multiple=False, albedo=0.9)
+        t_ren = (time.perf_counter() - t0) / (len(sub_r) * args.spp)
     # one step: 4 masks x (npix transmittance rays + npix*spp samples) at full mask cost
-    step_s = 4 * npix * (t_tau + args.spp * t_ren)
+    step_s = 4 * npix * (t_tau + spp_r * t_ren)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or 1)
     return {"value": round(units / step_s / 1e6, 6), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
-            "sample": "%d transmittance rays and %d rays x %d spp single scattering at the full mask, "
-                      "scaled to one step" % (len(sub), len(sub_r), args.spp),
+            "sample": ("%d transmittance rays" % len(sub)) +
+                      (" and %d rays x %d spp single scattering" % (len(sub_r), spp_r) if spp_r else "") +
+                      " at the full mask, scaled to one step",
             "tau_ms_per_ray": round(1e3 * t_tau, 4), "render_ms_per_sample": round(1e3 * t_ren, 3)}
 
 

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ params
                                                 const BoundsPartial* __restrict__ bnd, const uint32_t* __restrict__ perm,
                                                 float4* __restrict__ prims, float* __restrict__ aabb,
                                                 uint64_t* __restrict__ cellor, float* __restrict__ kw,
-                                                float4* __restrict__ aux) {
+                                                float4* __restrict__ aux, double* __restrict__ A64) {
     int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     int i = (int)perm[j];
@@ -356,6 +356,7 @@ __global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ params
             for (int k = 0; k < 3; ++k) acc += R[a][k] * R[b][k] / (s[k] * s[k]);
             A[idx++] = acc;
         }
+    for (int k = 0; k < 6; ++k) A64[(size_t)j * 6 + k] = A[k];
     double amp = (double)rho * (double)p[14] / (4.0 * GF_PI * s[0] * s[1] * s[2]);
     float4* rec = prims + (size_t)j * 4;
     rec[0] = make_float4(p[0], p[1], p[2], p[13]);
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ params
     rec[3] = make_float4(p[12], (float)amp, __int_as_float(cell), __int_as_float(i));
     double qn = sqrt(((double)p[3] * p[3] + (double)p[4] * p[4]) + (double)p[5] * p[5] + (double)p[6] * p[6]);
     float4* ax = aux + (size_t)j * 3;
-    ax[0] = make_float4((float)qh[0], (float)qh[1], (float)qh[2], (float)qh[3]);
+    ax[0] = make_float4(p[3], p[4], p[5], p[6]);
     ax[1] = make_float4((float)qn, p[7], p[8], p[9]);
     ax[2] = make_float4(p[14], (float)((double)rho / (4.0 * GF_PI * s[0] * s[1] * s[2])), 0.0f, 0.0f);
     // |k_W| = |S R^T omega| for the per-cell medians
@@ -439,9 +440,11 @@ __global__ __launch_bounds__(256) void k_tnodes(int n, const int32_t* __restrict
 
 // ---------------------------------------------------------------------------
 // 8. majorant grid: per voxel and cell, sum over primitives whose leaf box
-//    meets the voxel of rho |alpha| c exp(-m / 2), m = (distance from mu to the
-//    voxel)^2 / s_max^2 <= min of the Mahalanobis form over the voxel.  Sums
-//    are exact fixed-point integers (order independent), rounded up.
+//    meets the voxel of rho |alpha| c exp(-m / 2), with m a lower bound of the
+//    Mahalanobis form over the voxel: the larger of |d|^2 / s_max^2 and
+//    max_a d_a^2 / Sigma_aa (d = distance from mu to the voxel per axis; the
+//    level set {M <= m} lies inside |x_a - mu_a| <= sqrt(m Sigma_aa)).  Sums are
+//    exact fixed-point integers (order independent), rounded up.
 // ---------------------------------------------------------------------------
 #define GRID_FIX 1048576.0  // 2^20
 
@@ -456,6 +459,13 @@ __global__ __launch_bounds__(256) void k_grid_splat(const float* __restrict__ pa
     int cell = __float_as_int(prims[(size_t)j * 4 + 3].z);
     float smax = fmaxf(p[7], fmaxf(p[8], p[9]));
     double c = (double)rho * fabs((double)p[14]) / (pow(2.0 * GF_PI, 1.5) * (double)p[7] * p[8] * p[9]);
+    double R[3][3], qh[4];
+    rotation64(p, R, qh);
+    float isd2[3];
+    for (int a = 0; a < 3; ++a) {
+        double t0 = R[a][0] * p[7], t1 = R[a][1] * p[8], t2 = R[a][2] * p[9];
+        isd2[a] = (float)(1.0 / (t0 * t0 + t1 * t1 + t2 * t2));
+    }
     const float* bx = aabb + (size_t)(n - 1 + j) * 6;
     int i0[3], i1[3];
     float lo[3] = {glo.x, glo.y, glo.z}, h[3] = {gh.x, gh.y, gh.z};
@@ -470,8 +480,10 @@ __global__ __launch_bounds__(256) void k_grid_splat(const float* __restrict__ pa
             float vy0 = lo[1] + y * h[1], dy = fmaxf(0.0f, fmaxf(vy0 - p[1], p[1] - (vy0 + h[1])));
             for (int x = i0[0]; x <= i1[0]; ++x) {
                 float vx0 = lo[0] + x * h[0], dx = fmaxf(0.0f, fmaxf(vx0 - p[0], p[0] - (vx0 + h[0])));
-                // shrink the distance slightly so rounding never over-estimates it
-                float m = (dx * dx + dy * dy + dz * dz) * inv2 * 0.999f;
+                float m1 = (dx * dx + dy * dy + dz * dz) * inv2;
+                float m2 = fmaxf(fmaxf(dx * dx * isd2[0], dy * dy * isd2[1]), dz * dz * isd2[2]);
+                // shrink slightly so float32 rounding never over-estimates the bound
+                float m = fmaxf(m1, m2) * 0.999f;
                 double v = c * exp(-0.5 * (double)m);
                 unsigned long long q = (unsigned long long)ceil(v * GRID_FIX);
                 if (q) atomicAdd(&acc[((size_t)(z * G + y) * G + x) * GF_NCELLS + cell], q);
@@ -491,6 +503,12 @@ __global__ __launch_bounds__(256) void k_grid_final(const unsigned long long* __
 // ---------------------------------------------------------------------------
 // masks
 // ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cells_morton(const float4* __restrict__ prims, int n,
+                                                      int32_t* __restrict__ out) {
+    int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n) out[j] = __float_as_int(prims[(size_t)j * 4 + 3].z);
+}
+
 __global__ __launch_bounds__(256) void k_cells_export(const float4* __restrict__ prims, int n,
                                                       int32_t* __restrict__ out) {
     int j = blockIdx.x * 256 + threadIdx.x;
@@ -504,7 +522,7 @@ __global__ __launch_bounds__(256) void k_cells_export(const float4* __restrict__
 // ---------------------------------------------------------------------------
 static gf_status scene_free(gf_scene_s* s) {
     if (!s) return GF_OK;
-    void* ptrs[] = {s->prims, s->aux, s->nodes, s->grid, s->keys, s->perm, s->left, s->right, s->parent, s->aabb, s->cellor};
+    void* ptrs[] = {s->prims, s->aux, s->A64, s->nodes, s->grid, s->keys, s->perm, s->left, s->right, s->parent, s->aabb, s->cellor};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete s;
@@ -560,6 +578,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     size_t total = 0;
     GF_TRY(dalloc(&s->prims, (size_t)n * 4, &total));
     GF_TRY(dalloc(&s->aux, (size_t)n * 3, &total));
+    GF_TRY(dalloc(&s->A64, (size_t)n * 6, &total));
     GF_TRY(dalloc(&s->nodes, (size_t)std::max<int64_t>(n - 1, 1), &total));
     GF_TRY(dalloc(&s->grid, (size_t)G * G * G * GF_NCELLS, &total));
     GF_TRY(dalloc(&s->keys, (size_t)n, &total));
@@ -641,7 +660,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     if (n > 1) k_karras<<<nblk(n - 1), 256, 0, sm>>>(s->keys, ni, s->left, s->right, s->parent);
     // 5. records and leaves
     k_leaves<<<nblk(n), 256, 0, sm>>>(params, ni, r, s->rho, parts, (const uint32_t*)s->perm, s->prims, s->aabb,
-                                      s->cellor, kw, s->aux);
+                                      s->cellor, kw, s->aux, s->A64);
     // 6-7. refit and traversal records
     if (n > 1) {
         GF_STRY(hipMemsetAsync(visits, 0, sizeof(int) * (n - 1), sm) == hipSuccess
@@ -660,21 +679,20 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
         GF_STRY(hipMemcpyAsync(&hdepth, visits, sizeof(int), hipMemcpyDeviceToHost, sm) == hipSuccess
                     ? GF_OK : gf_hip_check(hipGetLastError(), "depth copy"));
     std::vector<float> hkw(n);
-    std::vector<float4> hrec3(n);
+    std::vector<int32_t> hcell(n);
     GF_STRY(hipMemcpyAsync(root, s->aabb, sizeof(root), hipMemcpyDeviceToHost, sm) == hipSuccess
                 ? GF_OK : gf_hip_check(hipGetLastError(), "root copy"));
     GF_STRY(hipMemcpyAsync(hkw.data(), kw, sizeof(float) * n, hipMemcpyDeviceToHost, sm) == hipSuccess
                 ? GF_OK : gf_hip_check(hipGetLastError(), "kw copy"));
-    GF_STRY(hipMemcpy2DAsync(hrec3.data(), sizeof(float4), s->prims + 3, 4 * sizeof(float4), sizeof(float4), n,
-                             hipMemcpyDeviceToHost, sm) == hipSuccess
+    k_cells_morton<<<nblk(n), 256, 0, sm>>>(s->prims, ni, (int32_t*)v2);
+    GF_STRY(hipMemcpyAsync(hcell.data(), v2, sizeof(int32_t) * n, hipMemcpyDeviceToHost, sm) == hipSuccess
                 ? GF_OK : gf_hip_check(hipGetLastError(), "cell copy"));
     GF_STRY(hipStreamSynchronize(sm) == hipSuccess ? GF_OK : gf_hip_check(hipGetLastError(), "sync"));
     s->depth = hdepth;
     {
         std::vector<std::vector<float>> per(GF_NCELLS);
         for (int64_t j = 0; j < n; ++j) {
-            int c;
-            memcpy(&c, &hrec3[j].z, sizeof(int));
+            int c = hcell[j];
             per[c].push_back(hkw[j]);
         }
         s->nonempty = 0;
@@ -806,6 +824,7 @@ SceneView gf_scene_view(const gf_scene_s* s) {
     v.nodes = s->nodes;
     v.grid = s->grid;
     v.aux = s->aux;
+    v.A64 = s->A64;
     v.n = (int)s->n;
     v.r = s->r;
     v.r2 = s->r * s->r;

@@ -112,8 +112,8 @@ static __device__ __forceinline__ void moments(const HitGeom& H, float Om, Cf* m
 static __device__ void hit_grad(const PrimF& P, const float4* __restrict__ auxp, const HitGeom& H, const RayD& R,
                                 float r2, float gr, float* out) {
     float4 x0 = auxp[0], x1 = auxp[1], x2 = auxp[2];
-    float qw = x0.x, qx = x0.y, qy = x0.z, qz = x0.w;
     float qn = x1.x, s[3] = {x1.y, x1.z, x1.w};
+    float qw = x0.x / qn, qx = x0.y / qn, qy = x0.z / qn, qz = x0.w / qn;
     float alpha = x2.x, amp1 = x2.y;
     const float sq2pi = 0.79788456080286535588f;
     float n = (float)H.n, inv_n = (float)H.inv_n;
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_tau_bwd(SceneView S, MaskView M, const 
 #pragma unroll
         for (int k = 0; k < 15; ++k) g[k] = 0.0f;
         HitGeom H;
-        bool hit = active && hit_geom(P, R, S.r2, H);
+        bool hit = active && hit_geom(P, R, S.r2, S.A64 + (size_t)j * 6, H);
         if (hit) hit_grad(P, S.aux + (size_t)j * 3, H, R, S.r2, gr, g);
         if (!__ballot(hit)) return;
         float* dst = dparams + (size_t)P.orig * 15;

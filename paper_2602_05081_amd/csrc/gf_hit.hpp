@@ -49,6 +49,29 @@ static __device__ __forceinline__ float2 wofz_weideman(float x, float y, const f
     return make_float2(wr, wi);
 }
 
+#define WEID64_N 32
+
+// The same rational approximation in binary64 with N = 32 (coefficients `a`,
+// highest power first); used only for ill-conditioned hits.
+static __device__ __forceinline__ void wofz_weideman64(double x, double y, const double* __restrict__ a, double L,
+                                                       double* wr, double* wi) {
+    double dr = L + y, di = -x;
+    double nr = L - y, ni = x;
+    double inv = 1.0 / (dr * dr + di * di);
+    double ir = dr * inv, ii = -di * inv;
+    double zr = nr * ir - ni * ii, zi = nr * ii + ni * ir;
+    double pr = a[0], pi = 0.0;
+    for (int k = 1; k < WEID64_N; ++k) {
+        double tr = pr * zr - pi * zi + a[k];
+        pi = pr * zi + pi * zr;
+        pr = tr;
+    }
+    double i2r = ir * ir - ii * ii, i2i = 2.0 * ir * ii;
+    const double isp = 0.56418958354775628695;
+    *wr = 2.0 * (pr * i2r - pi * i2i) + isp * ir;
+    *wi = 2.0 * (pr * i2i + pi * i2r) + isp * ii;
+}
+
 struct PrimF {
     float mux, muy, muz, phi;
     float a00, a01, a02, a11, a12, a22;
@@ -79,35 +102,55 @@ struct HitGeom {
     double thc;   // theta in cycles (phase at the closest point)
     double omc;   // Omega in cycles per whitened unit
     float h2, half, ua, ub;
+    double h2d, halfd, uad, ubd;  // binary64 versions for ill-conditioned hits
     bool enda, endb;
 };
 
-static __device__ __forceinline__ bool hit_geom(const PrimF& P, const RayD& R, float r2, HitGeom& H) {
+// Geometry from A (a00 a01 a02 a11 a12 a22).  Returns 0 when the clipped
+// chord is empty, 1 on a hit, 2 (float32 path only) when h^2 lies within
+// [r^2 - 0.05, r^2 + 0.01) and must be redone with binary64 A.
+static __device__ __forceinline__ int hit_geom_a(const PrimF& P, const RayD& R, float r2, const double* A,
+                                                 bool h2_double, HitGeom& H) {
     double dx = R.ox - P.mux, dy = R.oy - P.muy, dz = R.oz - P.muz;
-    double a00 = P.a00, a01 = P.a01, a02 = P.a02, a11 = P.a11, a12 = P.a12, a22 = P.a22;
-    double avx = a00 * R.vx + a01 * R.vy + a02 * R.vz;
-    double avy = a01 * R.vx + a11 * R.vy + a12 * R.vz;
-    double avz = a02 * R.vx + a12 * R.vy + a22 * R.vz;
+    double avx = A[0] * R.vx + A[1] * R.vy + A[2] * R.vz;
+    double avy = A[1] * R.vx + A[3] * R.vy + A[4] * R.vz;
+    double avz = A[2] * R.vx + A[4] * R.vy + A[5] * R.vz;
     double a = R.vx * avx + R.vy * avy + R.vz * avz;
     double beta = dx * avx + dy * avy + dz * avz;
     double inv_a = 1.0 / a;
     double tc = -beta * inv_a;
     double ycx = dx + tc * R.vx, ycy = dy + tc * R.vy, ycz = dz + tc * R.vz;
-    float yx = (float)ycx, yy = (float)ycy, yz = (float)ycz;
-    float h2 = yx * (P.a00 * yx + P.a01 * yy + P.a02 * yz) + yy * (P.a01 * yx + P.a11 * yy + P.a12 * yz) +
-               yz * (P.a02 * yx + P.a12 * yy + P.a22 * yz);
-    if (!(h2 < r2)) return false;
+    double h2d;
+    float h2;
+    if (h2_double) {
+        h2d = ycx * (A[0] * ycx + A[1] * ycy + A[2] * ycz) + ycy * (A[1] * ycx + A[3] * ycy + A[4] * ycz) +
+              ycz * (A[2] * ycx + A[4] * ycy + A[5] * ycz);
+        h2 = (float)h2d;
+        if (!(h2d < (double)r2)) return 0;
+    } else {
+        float yx = (float)ycx, yy = (float)ycy, yz = (float)ycz;
+        h2 = yx * (P.a00 * yx + P.a01 * yy + P.a02 * yz) + yy * (P.a01 * yx + P.a11 * yy + P.a12 * yz) +
+             yz * (P.a02 * yx + P.a12 * yy + P.a22 * yz);
+        if (!(h2 < r2 + 0.01f)) return 0;
+        if (h2 > r2 - 0.05f) return 2;
+        h2d = h2;
+    }
     double n = sqrt(a);
     double inv_n = n * inv_a;
-    float half = sqrtf(r2 - h2);
-    double hn = (double)half * inv_n;
+    double halfd = sqrt((double)r2 - h2d);
+    float half = (float)halfd;
+    double hn = halfd * inv_n;
     double tin = tc - hn, tout = tc + hn;
     double ta = fmax((double)R.tmin, tin), tb = fmin((double)R.tmax, tout);
-    if (!(ta < tb)) return false;
+    if (!(ta < tb)) return 0;
     H.enda = !((double)R.tmin > tin);
     H.endb = !((double)R.tmax < tout);
-    H.ua = H.enda ? -half : (float)(n * (ta - tc));
-    H.ub = H.endb ? half : (float)(n * (tb - tc));
+    H.uad = H.enda ? -halfd : n * (ta - tc);
+    H.ubd = H.endb ? halfd : n * (tb - tc);
+    H.ua = (float)H.uad;
+    H.ub = (float)H.ubd;
+    H.h2d = h2d;
+    H.halfd = halfd;
     H.tc = tc;
     H.n = n;
     H.inv_n = inv_n;
@@ -118,20 +161,15 @@ static __device__ __forceinline__ bool hit_geom(const PrimF& P, const RayD& R, f
     H.half = half;
     H.thc = (double)P.fx * ycx + (double)P.fy * ycy + (double)P.fz * ycz + (double)P.phi * GF_INV_2PI;
     H.omc = ((double)P.fx * R.vx + (double)P.fy * R.vy + (double)P.fz * R.vz) * inv_n;
-    return true;
+    return 1;
 }
 
-// Re{ e^{i theta} E(u) } / 1  (see the header of this file)
-static __device__ __forceinline__ float re_theta_E(float u, float Om, float eO, float cth, double thc, double omc,
-                                                   const float* __restrict__ wa, float wL) {
-    const float is2 = 0.70710678118654752440f;
-    float au = fabsf(u);
-    float sg = u < 0.0f ? -1.0f : 1.0f;
-    float2 w = wofz_weideman(sg * Om * is2, au * is2, wa, wL);
-    float sp, cp;
-    sincos2pi(frac_cycles(thc + (double)u * omc), &sp, &cp);
-    float eu = __expf(-0.5f * u * u);
-    return sg * (eO * cth - eu * (cp * w.x - sp * w.y));
+// Chord geometry of one hit from the binary64 Sigma^-1 of primitive j;
+// false when the clipped chord is empty.
+static __device__ __forceinline__ bool hit_geom(const PrimF& P, const RayD& R, float r2,
+                                                const double* __restrict__ A64j, HitGeom& H) {
+    double A[6] = {A64j[0], A64j[1], A64j[2], A64j[3], A64j[4], A64j[5]};
+    return hit_geom_a(P, R, r2, A, true, H) == 1;
 }
 
 // Gauss-Legendre, 8 nodes on [-1, 1] (positive half; the rule is symmetric)
@@ -140,29 +178,75 @@ __constant__ static const float c_gl8x[4] = {0.18343464249564980f, 0.52553240991
 __constant__ static const float c_gl8w[4] = {0.36268378337836198f, 0.31370664587788729f, 0.22238103445337447f,
                                              0.10122853629037626f};
 
-// int_{ua}^{ub} exp(-u^2/2) cos(psi(u)) du by 8-point Gauss-Legendre
-static __device__ __forceinline__ float gl8_segment(float ua, float ub, double thc, double omc) {
-    float c = 0.5f * (ua + ub), h = 0.5f * (ub - ua);
+// int_{ua}^{ub} exp(-u^2/2) cos(psi(u)) du by composite 8-point Gauss-Legendre
+// on `panels` equal panels
+static __device__ float gl8_segment(float ua, float ub, double thc, double omc, int panels) {
+    float w = (ub - ua) / panels;
     float acc = 0.0f;
+    for (int p = 0; p < panels; ++p) {
+        float c = ua + (p + 0.5f) * w, h = 0.5f * w;
+        float part = 0.0f;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        float d = h * c_gl8x[k];
-        float u1 = c - d, u2 = c + d;
-        float s1, c1, s2, c2;
-        sincos2pi(frac_cycles(thc + (double)u1 * omc), &s1, &c1);
-        sincos2pi(frac_cycles(thc + (double)u2 * omc), &s2, &c2);
-        acc += c_gl8w[k] * (__expf(-0.5f * u1 * u1) * c1 + __expf(-0.5f * u2 * u2) * c2);
+        for (int k = 0; k < 4; ++k) {
+            float d = h * c_gl8x[k];
+            float u1 = c - d, u2 = c + d;
+            float s1, c1, s2, c2;
+            sincos2pi(frac_cycles(thc + (double)u1 * omc), &s1, &c1);
+            sincos2pi(frac_cycles(thc + (double)u2 * omc), &s2, &c2);
+            part += c_gl8w[k] * (__expf(-0.5f * u1 * u1) * c1 + __expf(-0.5f * u2 * u2) * c2);
+        }
+        acc += part * h;
     }
-    return acc * h;
+    return acc;
+}
+
+// e^{-u^2/2} Re{e^{i psi(u)} w((sgn(u) Omega + i|u|)/sqrt 2)}: the part of
+// Re{e^{i theta} E(u)} that depends on the end point
+static __device__ __forceinline__ float tail_term(float u, float Om, double thc, double omc,
+                                                  const float* __restrict__ wa, float wL) {
+    const float is2 = 0.70710678118654752440f;
+    float sg = u < 0.0f ? -1.0f : 1.0f;
+    float2 w = wofz_weideman(sg * Om * is2, fabsf(u) * is2, wa, wL);
+    float sp, cp;
+    sincos2pi(frac_cycles(thc + (double)u * omc), &sp, &cp);
+    return __expf(-0.5f * u * u) * (cp * w.x - sp * w.y);
+}
+
+// The closed form entirely in binary64 (for hits whose float32 closed form
+// cancels by more than a factor 16).
+static __device__ float hit_value64(const PrimF& P, const HitGeom& H, const double* __restrict__ wa, double wL) {
+    const double is2 = 0.70710678118654752440;
+    double Om = 2.0 * GF_PI * H.omc;
+    double eO = exp(-0.5 * Om * Om);
+    double sth, cth;
+    sincospi(2.0 * (H.thc - rint(H.thc)), &sth, &cth);
+    double us[2] = {H.uad, H.ubd};
+    double f[2];
+    for (int e = 0; e < 2; ++e) {
+        double u = us[e];
+        double sg = u < 0.0 ? -1.0 : 1.0;
+        double wr, wi;
+        wofz_weideman64(sg * Om * is2, fabs(u) * is2, wa, wL, &wr, &wi);
+        double c = H.thc + u * H.omc;
+        double sp, cp;
+        sincospi(2.0 * (c - rint(c)), &sp, &cp);
+        f[e] = sg * (eO * cth - exp(-0.5 * u * u) * (cp * wr - sp * wi));
+    }
+    double pre = (double)P.amp * H.inv_n * exp(-0.5 * H.h2d);
+    return (float)(pre * (f[1] - f[0]));
 }
 
 // tau_i (including rho alpha) of one hit with a non-empty chord.
-// Short segments: the difference E(u_b) - E(u_a) cancels in float32, so when
-// len (1 + |Omega| + max|u|) < 4 the integrand exp(-u^2/2) cos psi(u) (smooth
-// there) is integrated by 8-point Gauss-Legendre instead (error below 1e-8
-// relative); below 1e-4 the midpoint rule is used.
+// Closed form: tau_i = pre Re{e^{i theta}[E(u_b) - E(u_a)]}, with
+// Re{e^{i theta}E(u)} = sgn(u) [exp(-Omega^2/2) cos theta - tail_term(u)].
+// Where that difference cancels (the segment integral is much smaller than
+// its terms, or the segment is short) float32 loses the digits:
+// below 1e-4 whitened units the midpoint rule is used; short segments
+// (len (1 + |Omega| + max|u|) < 4) use 8-point Gauss-Legendre; where the
+// float32 closed form cancels by more than a factor 16 it is redone in
+// binary64.
 static __device__ __forceinline__ float hit_value(const PrimF& P, const HitGeom& H, const float* __restrict__ wa,
-                                                  float wL) {
+                                                  float wL, const double* __restrict__ wa64, double wL64) {
     const float sq2pi = 0.79788456080286535588f;  // sqrt(2/pi)
     float Om = (float)(2.0 * GF_PI * H.omc);
     float pre = P.amp * (float)H.inv_n * __expf(-0.5f * H.h2);
@@ -174,26 +258,31 @@ static __device__ __forceinline__ float hit_value(const PrimF& P, const HitGeom&
         return pre * sq2pi * len * __expf(-0.5f * um * um) * cp;
     }
     float q = len * (1.0f + fabsf(Om) + fmaxf(fabsf(H.ua), fabsf(H.ub)));
-    if (q < 4.0f) return pre * sq2pi * gl8_segment(H.ua, H.ub, H.thc, H.omc);
+    if (q < 4.0f) return pre * sq2pi * gl8_segment(H.ua, H.ub, H.thc, H.omc, 1);
     float sth, cth;
     sincos2pi(frac_cycles(H.thc), &sth, &cth);
     float eO = __expf(-0.5f * Om * Om);
+    float val, mag;
     if (H.enda && H.endb) {
         // unclipped chord: E(h) - E(-h) = 2 Re E(h)
-        const float is2 = 0.70710678118654752440f;
-        float2 w = wofz_weideman(Om * is2, H.half * is2, wa, wL);
-        float sp, cp;
-        sincos2pi(frac_cycles((double)H.half * H.omc), &sp, &cp);
-        float reE = eO - __expf(-0.5f * H.half * H.half) * (cp * w.x - sp * w.y);
-        return 2.0f * pre * cth * reE;
+        float t = tail_term(H.half, Om, 0.0, H.omc, wa, wL);
+        float reE = eO - t;
+        val = 2.0f * cth * reE;
+        mag = 2.0f * fabsf(cth) * (eO + fabsf(t));
+    } else {
+        float sa = H.ua < 0.0f ? -1.0f : 1.0f, sb = H.ub < 0.0f ? -1.0f : 1.0f;
+        float tb = tail_term(H.ub, Om, H.thc, H.omc, wa, wL), ta = tail_term(H.ua, Om, H.thc, H.omc, wa, wL);
+        val = (sb - sa) * eO * cth - sb * tb + sa * ta;
+        mag = fabsf((sb - sa) * eO * cth) + fabsf(tb) + fabsf(ta);
     }
-    float fb = re_theta_E(H.ub, Om, eO, cth, H.thc, H.omc, wa, wL);
-    float fa = re_theta_E(H.ua, Om, eO, cth, H.thc, H.omc, wa, wL);
-    return pre * (fb - fa);
+    if (mag > 16.0f * fabsf(val)) return hit_value64(P, H, wa64, wL64);
+    return pre * val;
 }
 
-// Host: Weideman's coefficients for N = 16 (binary64 DFT, rounded to float32).
+// Host: Weideman's coefficients (binary64 DFT) for N = 16 rounded to float32,
+// and for N = 32 in binary64.
 void gf_weideman_coeffs(float* a, float* L);
+void gf_weideman_coeffs64(double* a, double* L);
 
 #define PK_WAVES 4
 

@@ -10,6 +10,9 @@
 //            holding both child boxes so one scalar load tests both children:
 //            [lbox lo/hi] [rbox lo/hi] [lchild rchild cells pad]; a child id
 //            c >= 0 is an internal node, c < 0 is the leaf (Morton index) ~c.
+//   A64    : n x 48 B, Sigma^-1 in binary64 for the chord geometry of the
+//            optical-depth and adjoint kernels (float32 rounding of an
+//            anisotropic Sigma^-1 moves h^2 by ~1e-5 relative).
 //   grid   : G^3 voxels x 12 cells of float32 majorants over the root box.
 //   canon  : the canonical LBVH arrays (keys, perm, left, right, parent,
 //            aabb, cellor) kept for export and refit.
@@ -38,6 +41,7 @@ struct SceneView {
     const TNode* __restrict__ nodes;
     const float* __restrict__ grid;
     const float4* __restrict__ aux;
+    const double* __restrict__ A64;  // Sigma^-1 in binary64, 6 per primitive (a00 a01 a02 a11 a12 a22)
     int n;
     float r, r2;
     int G;
@@ -63,8 +67,9 @@ struct gf_scene_s {
     float med[GF_NCELLS];
     // device memory
     float4* prims;
-    float4* aux;  // adjoint data, 3 x float4 per primitive (Morton order):
-                  // [qhat w x y z] [|q| s0 s1 s2] [alpha, rho/(4 pi s0 s1 s2), 0, 0]
+    double* A64;  // Sigma^-1 in binary64 (Morton order), 6 per primitive
+    float4* aux;  // adjoint data, 3 x float4 per primitive (Morton
+                  // order): [q w x y z (caller's)] [|q| s0 s1 s2] [alpha, rho/(4 pi s0 s1 s2), 0, 0]
     TNode* nodes;
     float* grid;
     uint64_t* keys;

@@ -17,29 +17,42 @@
 
 __constant__ float c_weid[WEID_N];
 __constant__ float c_weidL;
+__constant__ double c_weid64[WEID64_N];
+__constant__ double c_weidL64;
 
-void gf_weideman_coeffs(float* a, float* L) {
-    const int N = WEID_N, M = 2 * N, M2 = 2 * M;
+// Weideman's coefficients: f(t) = exp(-t^2)(L^2 + t^2) sampled at
+// t = L tan(theta/2), theta = k pi / M, then the real part of the DFT of the
+// (fftshift-ed) samples; a[p] holds the coefficient of Z^(N-1-p).
+static void weideman(int N, double* a, double* Lout) {
+    const int M = 2 * N, M2 = 2 * M;
     const double Ld = sqrt(N / sqrt(2.0));
-    double f[M2];
+    double f[256];
     f[0] = 0.0;
     for (int k = -M + 1; k <= M - 1; ++k) {
         double th = k * GF_PI / M;
         double t = Ld * tan(0.5 * th);
         f[k + M] = exp(-t * t) * (Ld * Ld + t * t);
     }
-    // fftshift, then the real part of the DFT divided by M2
-    double y[M2];
+    double y[256];
     for (int i = 0; i < M2; ++i) y[i] = f[(i + M2 / 2) % M2];
-    double A[M2];
+    double A[256];
     for (int m = 0; m < M2; ++m) {
         double re = 0.0;
-        for (int j = 0; j < M2; ++j) re += y[j] * cos(2.0 * GF_PI * (double)j * m / M2);
+        for (int j = 0; j < M2; ++j) re += y[j] * cos(2.0 * GF_PI * (double)(((long)j * m) % M2) / M2);
         A[m] = re / M2;
     }
-    for (int p = 0; p < N; ++p) a[p] = (float)A[N - p];
+    for (int p = 0; p < N; ++p) a[p] = A[N - p];
+    *Lout = Ld;
+}
+
+void gf_weideman_coeffs(float* a, float* L) {
+    double ad[WEID_N], Ld;
+    weideman(WEID_N, ad, &Ld);
+    for (int p = 0; p < WEID_N; ++p) a[p] = (float)ad[p];
     *L = (float)Ld;
 }
+
+void gf_weideman_coeffs64(double* a, double* L) { weideman(WEID64_N, a, L); }
 
 static bool g_weid_ready[64];
 
@@ -51,6 +64,10 @@ gf_status gf_ensure_weideman_tau() {
     gf_weideman_coeffs(a, &L);
     GF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_weid), a, sizeof(a)));
     GF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_weidL), &L, sizeof(L)));
+    double a64[WEID64_N], L64;
+    gf_weideman_coeffs64(a64, &L64);
+    GF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_weid64), a64, sizeof(a64)));
+    GF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_weidL64), &L64, sizeof(L64)));
     if (dev >= 0 && dev < 64) g_weid_ready[dev] = true;
     return GF_OK;
 }
@@ -71,9 +88,9 @@ __global__ __launch_bounds__(256) void k_tau(SceneView S, MaskView M, const floa
         if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
         if (!active) return;
         HitGeom H;
-        if (!hit_geom(P, R, S.r2, H)) return;
+        if (!hit_geom(P, R, S.r2, S.A64 + (size_t)j * 6, H)) return;
         if (COUNT) ++nh;
-        else acc += (double)hit_value(P, H, c_weid, c_weidL);
+        else acc += (double)hit_value(P, H, c_weid, c_weidL, c_weid64, c_weidL64);
     });
     if (valid) {
         if (COUNT) {

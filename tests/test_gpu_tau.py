@@ -48,6 +48,11 @@ def _check_tau(got, ref_tau, ref_abs, ref_hits):
     err = np.abs(got.astype(np.float64) - ref_tau)
     tol = tau_tolerance(ref_abs)
     bad = err > tol
+    if bad.any():
+        worst = np.argsort(-(err / (tol + 1e-300)))[:5]
+        for k in worst:
+            print("ray %d: got %.9g ref %.9g sum|tau_i| %.6g hits %d ratio %.3g" %
+                  (k, got[k], ref_tau[k], ref_abs[k], ref_hits[k], err[k] / (tol[k] + 1e-300)), flush=True)
     assert not bad.any(), "rays over tolerance: %d, worst ratio %.3g" % (bad.sum(), (err / (tol + 1e-300)).max())
     assert np.all(got[ref_hits == 0] == 0.0)
 

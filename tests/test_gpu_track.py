@@ -141,7 +141,7 @@ def test_stochastic_primary_transmittance_exact_expectation():
 
 def test_render_deterministic_and_batch_independent():
     gf = require_gpu()
-    params, rho = W.scene("blob100k"), W.rho("blob100k")
+    params, rho = W.scene("tiny256"), W.rho("tiny256")
     scene = gf.Scene(dev(params), rho=rho)
     rays = dev(gen.pinhole_rays(64, 64))
     d = gf.render_desc(spp=2, multiple=True, albedo=0.9, hg_g=0.3, stochastic=True, seed=7)
