@@ -12,7 +12,7 @@
 
 #include "gf_hit.hpp"
 
-#define TR_THREADS 128
+#define TR_THREADS 64
 #define TR_STACK 64
 
 // Per-cell density weights w and majorant weights mw = min(w, MAJ_CAP).  The
@@ -137,115 +137,225 @@ static __device__ float point_density(const SceneView& S, const MaskView& M, con
     return acc;
 }
 
-// Voxel walk (Amanatides-Woo) of the ray segment [t0, t1] clipped to the grid.
-struct Dda {
-    int ix, iy, iz, sx, sy, sz;
-    float tmx, tmy, tmz, tdx, tdy, tdz;
-    float t, tend;
-    bool live;
+// ---------------------------------------------------------------------------
+// Local majorants along a ray (per-lane LBVH traversal restricted to a
+// segment).  Pass A accumulates, for TB_BINS equal bins of the segment, the sum
+// over every chord crossing the bin of rho w_c |alpha| c exp(-m/2) (m the
+// minimum of the Mahalanobis form over the bin: h^2 + n^2 (clamp(tc) - tc)^2):
+// a piecewise-constant majorant of |kappa| made only of primitives the ray
+// actually crosses.  Tentative points are drawn from it in rounds of up to
+// TB_PTS; pass B re-traverses the t-range of a round and adds every crossed
+// primitive's density at every point of the round (no per-point queries).
+// ---------------------------------------------------------------------------
+#define TB_BINS 32
+#define TB_PTS 8
+// Hard bound on tentative points per segment: a segment that would need more
+// (a majorant beyond any produced by the scenes here) is cut short there,
+// which keeps every wave's work finite.
+#define TB_MAX_TENT 65536
+
+struct Lane {
+    int* stk;     // TR_STACK entries, stride TR_THREADS
+    float* bins;  // TB_BINS
+    float* pt;    // TB_PTS tentative distances
+    float* pm;    // majorant at each point
+    float* pk;    // density at each point
 };
 
-static __device__ __forceinline__ bool dda_init(const SceneView& S, float ox, float oy, float oz, float vx, float vy,
-                                                float vz, float t0, float t1, Dda& D) {
-    float iv[3] = {1.0f / vx, 1.0f / vy, 1.0f / vz};
+// chord of primitive P with the ray in float32 (stochastic paths): returns
+// false when M < r^2 misses [ta, tb]; otherwise the chord [ci, co], the
+// closest-point parameter tc, n^2 = v.Av and h^2.
+struct ChordF {
+    float ci, co, tc, n2, h2;
+};
+
+static __device__ __forceinline__ bool chord_f32(const PrimF& P, float r2, float ox, float oy, float oz, float vx,
+                                                 float vy, float vz, float ta, float tb, ChordF& C,
+                                                 bool inclusive = false) {
+    float dx = ox - P.mux, dy = oy - P.muy, dz = oz - P.muz;
+    float avx = P.a00 * vx + P.a01 * vy + P.a02 * vz;
+    float avy = P.a01 * vx + P.a11 * vy + P.a12 * vz;
+    float avz = P.a02 * vx + P.a12 * vy + P.a22 * vz;
+    float a = vx * avx + vy * avy + vz * avz;
+    float tc = -(dx * avx + dy * avy + dz * avz) / a;
+    float yx = dx + tc * vx, yy = dy + tc * vy, yz = dz + tc * vz;
+    float h2 = yx * (P.a00 * yx + P.a01 * yy + P.a02 * yz) + yy * (P.a01 * yx + P.a11 * yy + P.a12 * yz) +
+               yz * (P.a02 * yx + P.a12 * yy + P.a22 * yz);
+    if (!(h2 < r2)) return false;
+    float hw = sqrtf((r2 - h2) / a);
+    C.ci = fmaxf(ta, tc - hw);
+    C.co = fminf(tb, tc + hw);
+    if (inclusive ? !(C.ci <= C.co) : !(C.ci < C.co)) return false;
+    C.tc = tc;
+    C.n2 = a;
+    C.h2 = h2;
+    return true;
+}
+
+// per-lane traversal of the nodes whose box meets [ta, tb] (and whose cells
+// carry weight); leaf(j) for each such leaf
+template <bool COUNT, class LeafFn>
+static __device__ __forceinline__ void lane_traverse(const SceneView& S, uint32_t cells, float ox, float oy, float oz,
+                                                     float vx, float vy, float vz, float ta, float tb,
+                                                     int* __restrict__ stk, Work& wk, LeafFn&& leaf) {
+    if (S.n == 1) {
+        leaf(0);
+        return;
+    }
+    const float ix = 1.0f / vx, iy = 1.0f / vy, iz = 1.0f / vz;
+    int sp = 0, node = 0;
+    for (;;) {
+        const TNode* nd = S.nodes + node;
+        if (COUNT) ++wk.nodes;
+        uint32_t c = nd->cells;
+        bool hl = (c & 0xffffu & cells) && slab_hit(nd->lbox, ox, oy, oz, ix, iy, iz, ta, tb);
+        bool hr = ((c >> 16) & cells) && slab_hit(nd->rbox, ox, oy, oz, ix, iy, iz, ta, tb);
+        int lc = nd->lchild, rc = nd->rchild;
+        if (hl && lc < 0) {
+            leaf(~lc);
+            hl = false;
+        }
+        if (hr && rc < 0) {
+            leaf(~rc);
+            hr = false;
+        }
+        if (hl && hr) {
+            stk[sp * TR_THREADS] = rc;
+            ++sp;
+            node = lc;
+        } else if (hl) {
+            node = lc;
+        } else if (hr) {
+            node = rc;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = stk[sp * TR_THREADS];
+        }
+    }
+}
+
+// clip [t0, t1] to the scene box
+static __device__ __forceinline__ bool clip_box(const SceneView& S, float ox, float oy, float oz, float vx, float vy,
+                                                float vz, float& t0, float& t1) {
     float o[3] = {ox, oy, oz}, v[3] = {vx, vy, vz};
-    float ta = t0, tb = t1;
     for (int a = 0; a < 3; ++a) {
-        float u0 = (S.glo[a] - o[a]) * iv[a], u1 = (S.ghi[a] - o[a]) * iv[a];
         if (v[a] == 0.0f) {
             if (o[a] < S.glo[a] || o[a] > S.ghi[a]) return false;
             continue;
         }
-        ta = fmaxf(ta, fminf(u0, u1));
-        tb = fminf(tb, fmaxf(u0, u1));
+        float iv = 1.0f / v[a];
+        float u0 = (S.glo[a] - o[a]) * iv, u1 = (S.ghi[a] - o[a]) * iv;
+        t0 = fmaxf(t0, fminf(u0, u1));
+        t1 = fminf(t1, fmaxf(u0, u1));
     }
-    if (!(ta < tb)) return false;
-    int idx[3], st[3];
-    float tm[3], td[3];
-    for (int a = 0; a < 3; ++a) {
-        float p = o[a] + ta * v[a];
-        int i = (int)floorf((p - S.glo[a]) * S.ginv[a]);
-        i = i < 0 ? 0 : (i >= S.G ? S.G - 1 : i);
-        idx[a] = i;
-        float h = 1.0f / S.ginv[a];
-        if (v[a] > 0.0f) {
-            st[a] = 1;
-            tm[a] = (S.glo[a] + (i + 1) * h - o[a]) * iv[a];
-            td[a] = h * iv[a];
-        } else if (v[a] < 0.0f) {
-            st[a] = -1;
-            tm[a] = (S.glo[a] + i * h - o[a]) * iv[a];
-            td[a] = -h * iv[a];
-        } else {
-            st[a] = 0;
-            tm[a] = INFINITY;
-            td[a] = INFINITY;
+    return t0 < t1;
+}
+
+template <bool COUNT>
+static __device__ void pass_majorant(const SceneView& S, const MaskView& M, const CellW& cw, float ox, float oy,
+                                     float oz, float vx, float vy, float vz, float ta, float tb, const Lane& L,
+                                     Work& wk) {
+    for (int k = 0; k < TB_BINS; ++k) L.bins[k * TR_THREADS] = 0.0f;
+    const float inv_dt = TB_BINS / (tb - ta), dt = (tb - ta) / TB_BINS;
+    lane_traverse<COUNT>(S, cw.cells, ox, oy, oz, vx, vy, vz, ta, tb, L.stk, wk, [&](int j) {
+        PrimF P = load_prim(S.prims, j);
+        if (COUNT) ++wk.prims;
+        float wgt = cw.mw[P.cell];
+        if (wgt == 0.0f) return;
+        if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
+        ChordF C;
+        if (!chord_f32(P, S.r2, ox, oy, oz, vx, vy, vz, ta, tb, C)) return;
+        float peak = wgt * fabsf(P.amp) * 0.79788456080286535588f * 1.0001f;  // rho w |alpha| c
+        int k0 = max(0, min(TB_BINS - 1, (int)floorf((C.ci - ta) * inv_dt)));
+        int k1 = max(0, min(TB_BINS - 1, (int)floorf((C.co - ta) * inv_dt)));
+        for (int k = k0; k <= k1; ++k) {
+            float blo = ta + k * dt, bhi = blo + dt;
+            float du = fminf(fmaxf(C.tc, blo), bhi) - C.tc;
+            // shrink the minimum slightly so float32 rounding never raises it
+            float m = (C.h2 + C.n2 * du * du) * 0.999f;
+            L.bins[k * TR_THREADS] += peak * __expf(-0.5f * m);
         }
-    }
-    D.ix = idx[0]; D.iy = idx[1]; D.iz = idx[2];
-    D.sx = st[0]; D.sy = st[1]; D.sz = st[2];
-    D.tmx = tm[0]; D.tmy = tm[1]; D.tmz = tm[2];
-    D.tdx = td[0]; D.tdy = td[1]; D.tdz = td[2];
-    D.t = ta;
-    D.tend = tb;
-    D.live = true;
-    return true;
+    });
 }
 
-// exit distance of the current voxel
-static __device__ __forceinline__ float dda_exit(const Dda& D) {
-    return fminf(fminf(D.tmx, D.tmy), fminf(D.tmz, D.tend));
+// density at the np points (sorted, within [pa, pb]) into L.pk
+template <bool COUNT>
+static __device__ void pass_density(const SceneView& S, const MaskView& M, const CellW& cw, float ox, float oy,
+                                    float oz, float vx, float vy, float vz, int np, const Lane& L, Work& wk) {
+    float pa = L.pt[0], pb = L.pt[(np - 1) * TR_THREADS];
+    for (int k = 0; k < np; ++k) L.pk[k * TR_THREADS] = 0.0f;
+    lane_traverse<COUNT>(S, cw.cells, ox, oy, oz, vx, vy, vz, pa, pb, L.stk, wk, [&](int j) {
+        PrimF P = load_prim(S.prims, j);
+        if (COUNT) ++wk.prims;
+        float wgt = cw.w[P.cell];
+        if (wgt == 0.0f) return;
+        if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
+        ChordF C;
+        if (!chord_f32(P, S.r2, ox, oy, oz, vx, vy, vz, pa, pb, C, true)) return;
+        float amp = wgt * P.amp * 0.79788456080286535588f;
+        for (int k = 0; k < np; ++k) {
+            float t = L.pt[k * TR_THREADS];
+            if (t < C.ci || t > C.co) continue;
+            float x = ox + t * vx, y = oy + t * vy, z = oz + t * vz;
+            float dx = x - P.mux, dy = y - P.muy, dz = z - P.muz;
+            float m = dx * (P.a00 * dx + P.a01 * dy + P.a02 * dz) + dy * (P.a01 * dx + P.a11 * dy + P.a12 * dz) +
+                      dz * (P.a02 * dx + P.a12 * dy + P.a22 * dz);
+            if (!(m < S.r2)) continue;
+            float ph = P.fx * dx + P.fy * dy + P.fz * dz + P.phi * (float)GF_INV_2PI;
+            float sn, cs;
+            sincos2pi(ph - rintf(ph), &sn, &cs);
+            L.pk[k * TR_THREADS] += amp * __expf(-0.5f * m) * cs;
+        }
+    });
 }
 
-static __device__ __forceinline__ void dda_step(const SceneView& S, Dda& D) {
-    float te = dda_exit(D);
-    D.t = fmaxf(D.t, te);
-    if (te >= D.tend) {
-        D.live = false;
-        return;
+// Draws the next round of tentative points from the binned majorant,
+// continuing from (t, bin).  Returns the number of points (0 when the
+// segment is exhausted).  The process restarts at each bin boundary
+// (memoryless).
+static __device__ __forceinline__ int draw_points(float ta, float tb, const Lane& L, float& t, int& bin, Rng& g) {
+    const float dt = (tb - ta) / TB_BINS;
+    int np = 0;
+    while (bin < TB_BINS && np < TB_PTS) {
+        float kb = L.bins[bin * TR_THREADS];
+        float bend = bin == TB_BINS - 1 ? tb : ta + (bin + 1) * dt;
+        if (!(kb > 0.0f)) {
+            t = bend;
+            ++bin;
+            continue;
+        }
+        float tn = t - __logf(g.u()) / kb;
+        if (tn >= bend) {
+            t = bend;
+            ++bin;
+            continue;
+        }
+        t = fmaxf(tn, nextafterf(t, INFINITY));  // strict progress in float32
+        L.pt[np * TR_THREADS] = t;
+        L.pm[np * TR_THREADS] = kb;
+        ++np;
     }
-    if (D.tmx <= D.tmy && D.tmx <= D.tmz) {
-        D.ix += D.sx;
-        D.tmx += D.tdx;
-        if (D.ix < 0 || D.ix >= S.G) D.live = false;
-    } else if (D.tmy <= D.tmz) {
-        D.iy += D.sy;
-        D.tmy += D.tdy;
-        if (D.iy < 0 || D.iy >= S.G) D.live = false;
-    } else {
-        D.iz += D.sz;
-        D.tmz += D.tdz;
-        if (D.iz < 0 || D.iz >= S.G) D.live = false;
-    }
-}
-
-static __device__ __forceinline__ int dda_voxel(const SceneView& S, const Dda& D) {
-    return (D.iz * S.G + D.iy) * S.G + D.ix;
+    return np;
 }
 
 // Ratio tracking over [t0, t1]: T = prod (1 - kappa / kbar).
 template <bool COUNT>
 static __device__ float ratio_track(const SceneView& S, const MaskView& M, const CellW& cw, float ox, float oy,
-                                    float oz, float vx, float vy, float vz, float t0, float t1, Rng& g,
-                                    int* __restrict__ stk, Work& wk) {
-    Dda D;
-    if (!dda_init(S, ox, oy, oz, vx, vy, vz, t0, t1, D)) return 1.0f;
-    float T = 1.0f;
-    while (D.live) {
-        if (COUNT) ++wk.voxels;
-        float te = dda_exit(D);
-        float kb = voxel_majorant(S, dda_voxel(S, D), cw.mw);
-        if (kb > 0.0f) {
-            float t = D.t;
-            for (;;) {
-                t -= __logf(g.u()) / kb;
-                if (t >= te) break;
-                if (COUNT) ++wk.tent;
-                float k = point_density<COUNT>(S, M, cw, ox + t * vx, oy + t * vy, oz + t * vz, stk, wk);
-                T *= 1.0f - k / kb;
-            }
-        }
-        dda_step(S, D);
+                                    float oz, float vx, float vy, float vz, float t0, float t1, Rng& g, const Lane& L,
+                                    Work& wk) {
+    float ta = t0, tb = t1;
+    if (!clip_box(S, ox, oy, oz, vx, vy, vz, ta, tb)) return 1.0f;
+    pass_majorant<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, ta, tb, L, wk);
+    float T = 1.0f, t = ta;
+    int bin = 0;
+    for (int drawn = 0; drawn < TB_MAX_TENT;) {
+        int np = draw_points(ta, tb, L, t, bin, g);
+        if (np == 0) break;
+        drawn += np;
+        if (COUNT) wk.tent += np;
+        pass_density<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, np, L, wk);
+        for (int k = 0; k < np; ++k) T *= 1.0f - L.pk[k * TR_THREADS] / L.pm[k * TR_THREADS];
     }
     return T;
 }
@@ -256,42 +366,51 @@ static __device__ float ratio_track(const SceneView& S, const MaskView& M, const
 template <bool COUNT>
 static __device__ bool delta_track(const SceneView& S, const MaskView& M, const CellW& cw, float ox, float oy,
                                    float oz, float vx, float vy, float vz, float t0, float t1, Rng& g, float* w,
-                                   float* tc, int* __restrict__ stk, Work& wk) {
-    Dda D;
-    if (!dda_init(S, ox, oy, oz, vx, vy, vz, t0, t1, D)) return false;
-    while (D.live) {
-        if (COUNT) ++wk.voxels;
-        float te = dda_exit(D);
-        float kb = voxel_majorant(S, dda_voxel(S, D), cw.mw);
-        if (kb > 0.0f) {
-            float t = D.t;
-            for (;;) {
-                t -= __logf(g.u()) / kb;
-                if (t >= te) break;
-                if (COUNT) ++wk.tent;
-                float k = point_density<COUNT>(S, M, cw, ox + t * vx, oy + t * vy, oz + t * vz, stk, wk);
-                float xi = g.u();
-                if (k >= 0.0f && k <= kb) {
-                    if (xi * kb < k) {
-                        *tc = t;
-                        return true;
-                    }
-                } else {
-                    float kn = kb - k;
-                    float Dn = fabsf(k) + fabsf(kn);
-                    if (xi * Dn < fabsf(k)) {
-                        *w *= copysignf(Dn / kb, k);
-                        *tc = t;
-                        return true;
-                    }
-                    *w *= copysignf(Dn / kb, kn);
+                                   float* tc, const Lane& L, Work& wk) {
+    float ta = t0, tb = t1;
+    if (!clip_box(S, ox, oy, oz, vx, vy, vz, ta, tb)) return false;
+    pass_majorant<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, ta, tb, L, wk);
+    float t = ta;
+    int bin = 0;
+    for (int drawn = 0; drawn < TB_MAX_TENT;) {
+        int np = draw_points(ta, tb, L, t, bin, g);
+        if (np == 0) return false;
+        drawn += np;
+        if (COUNT) wk.tent += np;
+        pass_density<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, np, L, wk);
+        for (int k = 0; k < np; ++k) {
+            float kap = L.pk[k * TR_THREADS], kb = L.pm[k * TR_THREADS];
+            float xi = g.u();
+            if (kap >= 0.0f && kap <= kb) {
+                if (xi * kb < kap) {
+                    *tc = L.pt[k * TR_THREADS];
+                    return true;
                 }
+            } else {
+                float kn = kb - kap;
+                float Dn = fabsf(kap) + fabsf(kn);
+                if (xi * Dn < fabsf(kap)) {
+                    *w *= copysignf(Dn / kb, kap);
+                    *tc = L.pt[k * TR_THREADS];
+                    return true;
+                }
+                *w *= copysignf(Dn / kb, kn);
             }
         }
-        dda_step(S, D);
     }
     return false;
 }
+
+// per-lane LDS of a TR_THREADS-wide block
+#define LANE_LDS                                                               \
+    __shared__ int stk_all[TR_STACK * TR_THREADS];                             \
+    __shared__ float fl_all[(TB_BINS + 3 * TB_PTS) * TR_THREADS];              \
+    Lane L;                                                                    \
+    L.stk = stk_all + threadIdx.x;                                             \
+    L.bins = fl_all + threadIdx.x;                                             \
+    L.pt = fl_all + TB_BINS * TR_THREADS + threadIdx.x;                        \
+    L.pm = fl_all + (TB_BINS + TB_PTS) * TR_THREADS + threadIdx.x;             \
+    L.pk = fl_all + (TB_BINS + 2 * TB_PTS) * TR_THREADS + threadIdx.x;
 
 static __device__ __forceinline__ void sample_sphere(Rng& g, float* d) {
     float u1 = g.u(), u2 = g.u();
@@ -371,7 +490,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_density(SceneView S, MaskView M,
 __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, const float* __restrict__ rays, int n,
                                                       int tile_w, int spp, uint64_t seed, float* __restrict__ Tm,
                                                       float* __restrict__ Tv) {
-    __shared__ int stk[TR_STACK * TR_THREADS];
+    LANE_LDS
     int gid = blockIdx.x * TR_THREADS + threadIdx.x;
     int idx = ray_of_tr(gid, n, tile_w);
     if (idx < 0) return;
@@ -383,8 +502,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, c
     for (int s = 0; s < spp; ++s) {
         Rng g;
         g.init(seed, (uint32_t)idx, (uint32_t)s, 1u);
-        float T = ratio_track<false>(S, M, cw, r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], g, stk + threadIdx.x,
-                                     wk);
+        float T = ratio_track<false>(S, M, cw, r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], g, L, wk);
         s1 += T;
         s2 += T * T;
     }
@@ -401,8 +519,8 @@ struct RenderArgs {
 // All samples of one ray; random streams keyed by (seed, key, sample).
 template <bool COUNT>
 static __device__ void render_ray(const SceneView& S, const MaskView& M, const RenderArgs& A, const float* r,
-                                  uint32_t key, int* __restrict__ stk, float* Lmean, float* Lvar, float* Tmean,
-                                  float* Tvar, Work& wk) {
+                                  uint32_t key, const Lane& ln, float* Lmean, float* Lvar, float* Tmean, float* Tvar,
+                                  Work& wk) {
     CellW fixed;
     fixed_weights(M, fixed);
     float s1 = 0.0f, s2 = 0.0f, q1 = 0.0f, q2 = 0.0f;
@@ -416,9 +534,9 @@ static __device__ void render_ray(const SceneView& S, const MaskView& M, const R
         for (int seg = 0;; ++seg) {
             CellW cw = fixed;
             if (A.stochastic) stochastic_weights(S, vx, vy, vz, g, cw);
-            if (seg == 0) Tp = ratio_track<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, t0, t1, gT, stk, wk);
+            if (seg == 0) Tp = ratio_track<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, t0, t1, gT, ln, wk);
             float tc;
-            if (!delta_track<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, t0, t1, g, &w, &tc, stk, wk)) {
+            if (!delta_track<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, t0, t1, g, &w, &tc, ln, wk)) {
                 L += w * A.env;
                 break;
             }
@@ -427,7 +545,7 @@ static __device__ void render_ray(const SceneView& S, const MaskView& M, const R
                 float d[3];
                 sample_sphere(g, d);
                 L += w * A.albedo *
-                     ratio_track<COUNT>(S, M, cw, x, y, z, d[0], d[1], d[2], 0.0f, INFINITY, g, stk, wk) * A.env;
+                     ratio_track<COUNT>(S, M, cw, x, y, z, d[0], d[1], d[2], 0.0f, INFINITY, g, ln, wk) * A.env;
                 break;
             }
             if (nsc >= A.max_scatter) break;
@@ -459,13 +577,13 @@ __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, 
                                                        float* __restrict__ Lv, float* __restrict__ Tm,
                                                        float* __restrict__ Tv,
                                                        unsigned long long* __restrict__ counters) {
-    __shared__ int stk_all[TR_STACK * TR_THREADS];
+    LANE_LDS
     int gid = blockIdx.x * TR_THREADS + threadIdx.x;
     int idx = ray_of_tr(gid, n, tile_w);
     if (idx < 0) return;
     float a, b, c, d;
     Work wk{};
-    render_ray<COUNT>(S, M, A, rays + (size_t)idx * 8, (uint32_t)idx, stk_all + threadIdx.x, &a, &b, &c, &d, wk);
+    render_ray<COUNT>(S, M, A, rays + (size_t)idx * 8, (uint32_t)idx, L, &a, &b, &c, &d, wk);
     if (COUNT) {
         atomicAdd(counters + 0, wk.tent);
         atomicAdd(counters + 1, wk.nodes);
@@ -497,7 +615,7 @@ struct ServeTile {
 
 __global__ __launch_bounds__(TR_THREADS) void k_render_tiles(const ServeReq* __restrict__ reqs,
                                                              const ServeTile* __restrict__ tiles, int blocks_per_tile) {
-    __shared__ int stk_all[TR_STACK * TR_THREADS];
+    LANE_LDS
     const ServeTile tl = tiles[blockIdx.x / blocks_per_tile];
     int local = (blockIdx.x % blocks_per_tile) * TR_THREADS + threadIdx.x;
     if (local >= tl.count) return;
@@ -505,8 +623,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_render_tiles(const ServeReq* __r
     int idx = tl.first + local;
     float a, b, c, d;
     Work wk{};
-    render_ray<false>(R.S, R.M, R.A, R.rays + (size_t)idx * 8, (uint32_t)idx, stk_all + threadIdx.x, &a, &b, &c, &d,
-                      wk);
+    render_ray<false>(R.S, R.M, R.A, R.rays + (size_t)idx * 8, (uint32_t)idx, L, &a, &b, &c, &d, wk);
     R.out[idx] = a;
 }
 
