@@ -31,7 +31,10 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 # bytes each unit of work must touch (per-unit figures; see the design notes)
-RAY_BYTES, OUT_BYTES, PRIM_BYTES, NODE_BYTES, VOXEL_BYTES = 32, 8, 60, 32, 48
+# optical depth: per ray, per child-box hit (half a 64 B node record), per chord
+# (a 60 B primitive record); tracking: per internal-node visit (its 64 B
+# record) and per primitive record read at a leaf
+RAY_BYTES, OUT_BYTES, PRIM_BYTES, NODE_BYTES, VISIT_BYTES = 32, 8, 60, 32, 64
 
 
 def parse():
@@ -143,8 +146,8 @@ def main():
         nn, nh = int(nodes.sum().item()), int(hits.sum().item())
         tau_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + PRIM_BYTES * nh + NODE_BYTES * nn)
         if args.render:
-            tent, qn, qp, vox = gf.gf_render_counts(scene, rays, desc(m), image_width=width)
-            ren_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + NODE_BYTES * qn + PRIM_BYTES * qp + VOXEL_BYTES * vox)
+            tent, qn, qp, nwin = gf.gf_render_counts(scene, rays, desc(m), image_width=width)
+            ren_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + VISIT_BYTES * qn + PRIM_BYTES * qp)
         else:
             ren_bytes.append(0)
     torch.cuda.synchronize()

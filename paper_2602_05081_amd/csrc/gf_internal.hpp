@@ -139,6 +139,9 @@ static __device__ __forceinline__ uint4 philox4x32(uint4 c, uint32_t k0, uint32_
     return c;
 }
 
+// uniform in (0, 1) from 32 random bits: ((x >> 8) + 0.5) 2^-24
+static __device__ __forceinline__ float unit_float(uint32_t x) { return ((float)(x >> 8) + 0.5f) * (1.0f / 16777216.0f); }
+
 // Counter-based stream: key = seed, counter = (a, b, block, tag).
 struct Rng {
     uint32_t k0, k1, a, b, tag, blk;
@@ -153,8 +156,8 @@ struct Rng {
         blk = 0;
         used = 4;
     }
-    // uniform in (0, 1): ((x >> 8) + 0.5) 2^-24
-    __device__ float u() {
+    // next 32 random bits of the stream
+    __device__ uint32_t bits() {
         if (used == 4) {
             buf = philox4x32(make_uint4(a, b, blk, tag), k0, k1);
             ++blk;
@@ -162,8 +165,10 @@ struct Rng {
         }
         uint32_t x = used == 0 ? buf.x : used == 1 ? buf.y : used == 2 ? buf.z : buf.w;
         ++used;
-        return ((float)(x >> 8) + 0.5f) * (1.0f / 16777216.0f);
+        return x;
     }
+    // uniform in (0, 1): ((x >> 8) + 0.5) 2^-24
+    __device__ float u() { return unit_float(bits()); }
 };
 
 static __device__ __forceinline__ bool mask_keep(const MaskView& m, int cell, int orig) {

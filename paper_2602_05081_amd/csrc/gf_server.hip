@@ -4,7 +4,8 @@
 // Memory: the server owns one device pool of `mem_budget` bytes, carved by a
 // first-fit allocator; an admitted request holds width*height*32 bytes of
 // camera rays there until its last tile completes.  No device allocation
-// happens while serving.
+// happens while serving; the tracking workspace of one batch is allocated
+// with the server.
 // Scheduling: requests wait in FIFO order until their rays fit the pool; an
 // admitted request's rays are generated on the device right away.  Each step
 // assembles one batch of up to `max_tiles` tiles of `tile_rays` rays, taking
@@ -27,7 +28,8 @@ gf_status gf_check_render_desc(const gf_render_desc* d, const char* who);
 gf_status gf_serve_fill_req(const gf_request* q, const float* rays, void* out_desc);
 size_t gf_serve_req_size();
 size_t gf_serve_tile_size();
-gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int tile_rays, hipStream_t sm);
+gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int tile_rays, float* ws, hipStream_t sm);
+size_t gf_serve_workspace_bytes(int max_tiles, int tile_rays);
 
 namespace {
 
@@ -60,6 +62,7 @@ struct gf_server_s {
     int tile_rays, max_tiles;
     hipStream_t stream;
     char* pool;
+    float* ws;  // tracking workspace of one batch (batches run in stream order)
     std::vector<FreeBlock> freel;  // sorted by offset, coalesced
     std::deque<Req*> queue;
     std::vector<Req*> active;
@@ -125,6 +128,7 @@ extern "C" gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_
     S->stream = (hipStream_t)stream;
     S->next_id = 1;
     S->pool = nullptr;
+    S->ws = nullptr;
     for (int k = 0; k < kSlots; ++k) {
         S->slot_busy[k] = false;
         S->hreq[k] = S->htile[k] = S->dreq[k] = S->dtile[k] = nullptr;
@@ -137,6 +141,8 @@ extern "C" gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_
     hipError_t e = hipMalloc((void**)&S->pool, S->budget);
     if (e != hipSuccess) return fail(e, "hipMalloc(pool)");
     S->freel.push_back(FreeBlock{0, S->budget});
+    e = hipMalloc((void**)&S->ws, gf_serve_workspace_bytes(max_tiles, tile_rays));
+    if (e != hipSuccess) return fail(e, "hipMalloc(workspace)");
     for (int k = 0; k < kSlots; ++k) {
         if ((e = hipHostMalloc((void**)&S->hreq[k], gf_serve_req_size() * max_tiles)) != hipSuccess)
             return fail(e, "hipHostMalloc");
@@ -164,6 +170,7 @@ extern "C" gf_status gf_server_destroy(gf_server S) {
         if (S->events[k]) (void)hipEventDestroy(S->events[k]);
     }
     if (S->pool) (void)hipFree(S->pool);
+    if (S->ws) (void)hipFree(S->ws);
     for (auto& kv : S->byid) delete kv.second;
     delete S;
     return GF_OK;
@@ -275,7 +282,7 @@ static gf_status launch_batch(gf_server_s* S) {
     for (auto& kv : rays_in) b.work.push_back(kv);
     GF_HIP(hipMemcpyAsync(S->dreq[slot], hreq, gf_serve_req_size() * nreq, hipMemcpyHostToDevice, S->stream));
     GF_HIP(hipMemcpyAsync(S->dtile[slot], htile, gf_serve_tile_size() * ntiles, hipMemcpyHostToDevice, S->stream));
-    gf_status st = gf_serve_launch(S->dreq[slot], S->dtile[slot], ntiles, S->tile_rays, S->stream);
+    gf_status st = gf_serve_launch(S->dreq[slot], S->dtile[slot], ntiles, S->tile_rays, S->ws, S->stream);
     if (st != GF_OK) return st;
     GF_HIP(hipEventRecord(b.ev, S->stream));
     S->slot_busy[slot] = true;

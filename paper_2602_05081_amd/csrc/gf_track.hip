@@ -1,44 +1,87 @@
-// Stochastic transport on the majorant grid: point density, ratio-tracking
+// Stochastic transport along rays: point density, ratio-tracking
 // transmittance, weighted delta tracking, single / multiple scattering with
 // fixed or per-segment stochastic masks (Sec. 3 radiative transfer; Sec. 4.5.1-
-// 4.5.2 and Appendix B for the masks; local majorants after the voxel
-// baseline's super-voxel grid).
+// 4.5.2 and Appendix B for the masks).
 //
-// Per lane: one ray (all its samples, so per-ray sums are deterministic and
-// independent of which rays share a wave).  A point-density query walks the
-// LBVH with a per-lane stack in LDS, descending into children whose box
-// contains the point and whose subtree holds a cell of non-zero weight.
+// Local majorant.  On a segment the tentative collisions form a Poisson
+// process whose intensity is the masked envelope
+//     mu(t) = sum_i rho m_c(i) |alpha_i| c_i exp(-M_i(x(t)) / 2) [M_i < r^2],
+// an upper bound of |kappa| built only from primitives the segment crosses
+// (m_c: majorant weight of cell c).  It is drawn as a superposition: on the
+// chord [ci, co] of primitive i a homogeneous process of rate
+// lambda_i = rho m |alpha_i| c_i exp(-h_i^2 / 2) (the envelope's maximum on
+// the line) is thinned with probability exp(-n_i^2 (t - tc_i)^2 / 2), which
+// leaves the chord's envelope as intensity.  One LBVH traversal proposes the
+// points, a second one evaluates kappa and mu at all of them.
+//
+// Windows.  A lane holds at most TK tentative points.  When a segment has
+// more, the buffer keeps the TK earliest and the window ends at the last of
+// them; the process is restarted just after it.  A Poisson process restarted
+// at one of its own points (a stopping time) is again Poisson, so each window
+// is an exact sample of the process restricted to it.
+//
+// Lanes.  One ray per lane with all its samples.  Every lane of a wave runs
+// the same steps (proposal traversal, evaluation traversal, decision) in each
+// iteration of one flat loop, whatever its path length: a lane whose sample
+// ends starts its next sample in the next iteration, so waves stay converged.
+// All random numbers of a sample come from one counter-based stream keyed by
+// (seed, ray, sample); a ray's result does not depend on the other rays of
+// the launch.
 #include <math.h>
 
 #include "gf_hit.hpp"
 
 #define TR_THREADS 64
-#define TR_STACK 64
-
-// Per-cell density weights w and majorant weights mw = min(w, MAJ_CAP).  The
-// cap bounds the work of a path that drew a heavily weighted (rarely drawn)
-// bin; ratio tracking and the signed-weight delta tracking stay unbiased when
-// the majorant falls below |kappa| (only their variance grows).
+#define TR_STACK 64  // deepest LBVH the per-lane traversal supports
+#define TS_LDS 24    // per-lane stack entries kept in LDS; deeper ones go to the workspace
+#define TK 32        // tentative points per window
+#define CQ 8         // leaf candidates a lane queues before the wave processes them
+// Majorant weight cap of a stochastic cell.  It bounds the work of a path
+// that drew a heavily weighted (rarely drawn) bin; ratio tracking and the
+// signed-weight delta tracking stay unbiased where the majorant falls below
+// |kappa| (only their variance grows).
 #define MAJ_CAP 16.0f
+// Hard bound on windows per segment (TK points each): a segment that would
+// need more is cut short there, which keeps every wave's work finite.
+#define MAX_WINDOWS 4096
+// Waves resident in one launch: each owns a workspace slice, and loops over
+// the launch's tiles with a grid stride.
+#define TR_RES_BLOCKS 4096
 
+// Workspace rows of a wave (each row: TR_THREADS lanes x 4 B).
+#define WS_KAP 0
+#define WS_MAJ TK
+#define WS_XI (2 * TK)
+#define WS_SPILL (3 * TK)
+#define WS_ROWS (3 * TK + TR_STACK - TS_LDS)
+
+// c_i / amp_i: the density's normalisation (2 pi)^-3/2 / (s0 s1 s2) over the
+// optical-depth amplitude 1 / (4 pi s0 s1 s2), i.e. sqrt(2 / pi)
+#define GF_NORM 0.79788456080286535588f
+
+// Per-cell density weight w_c and majorant weight m_c: 1 on the cells of
+// `cells` except `pick`, which carries (wp, mwp); 0 elsewhere.
 struct CellW {
-    float w[GF_NCELLS];
-    float mw[GF_NCELLS];
-    uint32_t cells;  // cells with non-zero weight
+    uint32_t cells;
+    int pick;
+    float wp, mwp;
+    __device__ float w(int c) const { return c == pick ? wp : (((cells >> c) & 1u) ? 1.0f : 0.0f); }
+    __device__ float mw(int c) const { return c == pick ? mwp : (((cells >> c) & 1u) ? 1.0f : 0.0f); }
 };
 
-static __device__ __forceinline__ void fixed_weights(const MaskView& M, CellW& cw) {
-#pragma unroll
-    for (int c = 0; c < GF_NCELLS; ++c) cw.w[c] = cw.mw[c] = ((M.cells >> c) & 1u) ? 1.0f : 0.0f;
-    cw.cells = M.cells;
+static __device__ __forceinline__ CellW fixed_weights(const MaskView& M) {
+    CellW cw;
+    cw.cells = M.cells & 0xFFFu;
+    cw.pick = -1;
+    cw.wp = cw.mwp = 0.0f;
+    return cw;
 }
 
 // Uniform + control variate over levels, importance sampling over bins:
 // level 0 keeps weight 1; one level l in 1..3 (probability 1/3) and one bin k
 // (probability w_k / W, w_k = exp(-m_lk^2 a_k^2 / 2), a_k = |v_k| / |v|) get
 // weight 3 W / w_k; every other cell weight 0.
-static __device__ __forceinline__ void stochastic_weights(const SceneView& S, float vx, float vy, float vz, Rng& g,
-                                                          CellW& cw) {
+static __device__ __forceinline__ CellW stochastic_weights(const SceneView& S, float vx, float vy, float vz, Rng& g) {
     float ul = g.u(), ub = g.u();
     int l = 1 + (int)(ul * 3.0f);
     l = l > 3 ? 3 : l;
@@ -65,19 +108,19 @@ static __device__ __forceinline__ void stochastic_weights(const SceneView& S, fl
         acc += wk[j];
         if (target < acc) break;
     }
-#pragma unroll
-    for (int c = 0; c < GF_NCELLS; ++c) cw.w[c] = cw.mw[c] = c < 3 ? 1.0f : 0.0f;
-    int pick = 3 * l + k;
-    cw.w[pick] = 3.0f * W / wk[k];
-    cw.mw[pick] = fminf(cw.w[pick], MAJ_CAP);
-    cw.cells = 0x7u | (1u << pick);
+    CellW cw;
+    cw.pick = 3 * l + k;
+    cw.cells = 0x7u | (1u << cw.pick);
+    cw.wp = 3.0f * W / wk[k];
+    cw.mwp = fminf(cw.wp, MAJ_CAP);
+    return cw;
 }
 
 // Work counters of the counting variants (per lane, summed at the end):
-// tentative collisions, internal nodes visited by point queries, primitive
-// records read at leaves, voxels walked.
+// accepted tentative points, internal nodes visited, primitive records read
+// at leaves, windows.
 struct Work {
-    unsigned long long tent, nodes, prims, voxels;
+    unsigned long long tent, nodes, prims, windows;
 };
 
 // kappa at x under per-cell weights (rho alpha c exp(-M/2) cos(psi) summed)
@@ -88,7 +131,7 @@ static __device__ float point_density(const SceneView& S, const MaskView& M, con
     auto leaf = [&](int j) {
         PrimF P = load_prim(S.prims, j);
         if (COUNT) ++wk.prims;
-        float wgt = cw.w[P.cell];
+        float wgt = cw.w(P.cell);
         if (wgt == 0.0f) return;
         if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
         float dx = x - P.mux, dy = y - P.muy, dz = z - P.muz;
@@ -98,7 +141,7 @@ static __device__ float point_density(const SceneView& S, const MaskView& M, con
         float ph = P.fx * dx + P.fy * dy + P.fz * dz + P.phi * (float)GF_INV_2PI;
         float s, c;
         sincos2pi(ph - rintf(ph), &s, &c);
-        acc += wgt * P.amp * 0.79788456080286535588f * __expf(-0.5f * m) * c;
+        acc += wgt * P.amp * GF_NORM * __expf(-0.5f * m) * c;
     };
     if (S.n == 1) {
         leaf(0);
@@ -138,40 +181,49 @@ static __device__ float point_density(const SceneView& S, const MaskView& M, con
 }
 
 // ---------------------------------------------------------------------------
-// Local majorants along a ray (per-lane LBVH traversal restricted to a
-// segment).  Pass A accumulates, for TB_BINS equal bins of the segment, the sum
-// over every chord crossing the bin of rho w_c |alpha| c exp(-m/2) (m the
-// minimum of the Mahalanobis form over the bin: h^2 + n^2 (clamp(tc) - tc)^2):
-// a piecewise-constant majorant of |kappa| made only of primitives the ray
-// actually crosses.  Tentative points are drawn from it in rounds of up to
-// TB_PTS; pass B re-traverses the t-range of a round and adds every crossed
-// primitive's density at every point of the round (no per-point queries).
+// per-lane memory: stack and tentative distances in LDS, the rest (point
+// densities, majorants, delta-tracking uniforms, stack spill) in the
+// launch's workspace, interleaved by lane so that a wave's rows coalesce
 // ---------------------------------------------------------------------------
-#define TB_BINS 32
-#define TB_PTS 8
-// Hard bound on tentative points per segment: a segment that would need more
-// (a majorant beyond any produced by the scenes here) is cut short there,
-// which keeps every wave's work finite.
-#define TB_MAX_TENT 65536
-
-struct Lane {
-    int* stk;     // TR_STACK entries, stride TR_THREADS
-    float* bins;  // TB_BINS
-    float* pt;    // TB_PTS tentative distances
-    float* pm;    // majorant at each point
-    float* pk;    // density at each point
+struct LaneMem {
+    int* stk;   // LDS, TS_LDS entries, stride TR_THREADS
+    int* cand;  // LDS, CQ queued leaf candidates, stride TR_THREADS
+    float* t;   // LDS, TK tentative distances, stride TR_THREADS
+    float* ws;  // workspace: row r at ws[r * TR_THREADS]
+    __device__ float& kap(int k) const { return ws[(WS_KAP + k) * TR_THREADS]; }
+    __device__ float& maj(int k) const { return ws[(WS_MAJ + k) * TR_THREADS]; }
+    __device__ float& xi(int k) const { return ws[(WS_XI + k) * TR_THREADS]; }
+    __device__ void push(int sp, int v) const {
+        if (sp < TS_LDS)
+            stk[sp * TR_THREADS] = v;
+        else
+            ((int*)ws)[(WS_SPILL + sp - TS_LDS) * TR_THREADS] = v;
+    }
+    __device__ int pop(int sp) const {
+        return sp < TS_LDS ? stk[sp * TR_THREADS] : ((const int*)ws)[(WS_SPILL + sp - TS_LDS) * TR_THREADS];
+    }
 };
 
-// chord of primitive P with the ray in float32 (stochastic paths): returns
-// false when M < r^2 misses [ta, tb]; otherwise the chord [ci, co], the
-// closest-point parameter tc, n^2 = v.Av and h^2.
+#define LANE_MEM(ws_base)                                                               \
+    __shared__ int stk_all[TS_LDS * TR_THREADS];                                        \
+    __shared__ int cand_all[CQ * TR_THREADS];                                           \
+    __shared__ float t_all[TK * TR_THREADS];                                            \
+    LaneMem lm;                                                                         \
+    lm.stk = stk_all + threadIdx.x;                                                     \
+    lm.cand = cand_all + threadIdx.x;                                                   \
+    lm.t = t_all + threadIdx.x;                                                         \
+    lm.ws = (ws_base) + (size_t)blockIdx.x * (WS_ROWS * TR_THREADS) + threadIdx.x;
+
+// chord of primitive P with the ray in float32: false when M < r^2 misses
+// [ta, tb]; otherwise the clipped chord [ci, co], the closest-point parameter
+// tc, n^2 = v.Av and h^2 (minimum of M on the line)
 struct ChordF {
     float ci, co, tc, n2, h2;
 };
 
 static __device__ __forceinline__ bool chord_f32(const PrimF& P, float r2, float ox, float oy, float oz, float vx,
                                                  float vy, float vz, float ta, float tb, ChordF& C,
-                                                 bool inclusive = false) {
+                                                 bool inclusive) {
     float dx = ox - P.mux, dy = oy - P.muy, dz = oz - P.muz;
     float avx = P.a00 * vx + P.a01 * vy + P.a02 * vz;
     float avy = P.a01 * vx + P.a11 * vy + P.a12 * vz;
@@ -192,45 +244,79 @@ static __device__ __forceinline__ bool chord_f32(const PrimF& P, float r2, float
     return true;
 }
 
-// per-lane traversal of the nodes whose box meets [ta, tb] (and whose cells
-// carry weight); leaf(j) for each such leaf
+// entry distance of the ray into box b within [tmin, tmax] (INFINITY: miss);
+// the same conservative test as slab_hit
+static __device__ __forceinline__ float slab_enter(const float* b, float ox, float oy, float oz, float ix, float iy,
+                                                   float iz, float tmin, float tmax) {
+    float t0x = (b[0] - ox) * ix, t1x = (b[3] - ox) * ix;
+    float t0y = (b[1] - oy) * iy, t1y = (b[4] - oy) * iy;
+    float t0z = (b[2] - oz) * iz, t1z = (b[5] - oz) * iz;
+    float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+    float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    return tn <= tf + fabsf(tf) * 1e-6f + 1e-30f ? tn : INFINITY;
+}
+
+// Per-lane front-to-back traversal of the nodes whose box meets [ta, tb]
+// and whose subtree holds a weighted cell; leaf(j) for each such leaf.
+// Leaves are not processed where they are found: a lane queues up to CQ of
+// them, and once every lane's queue is full (or its traversal over) the wave
+// processes the queues together, so the leaf work runs converged.  tb is
+// re-read at every node, so a leaf callback may shrink it and prune what
+// lies beyond.
 template <bool COUNT, class LeafFn>
 static __device__ __forceinline__ void lane_traverse(const SceneView& S, uint32_t cells, float ox, float oy, float oz,
-                                                     float vx, float vy, float vz, float ta, float tb,
-                                                     int* __restrict__ stk, Work& wk, LeafFn&& leaf) {
+                                                     float vx, float vy, float vz, float ta, const float& tb,
+                                                     const LaneMem& lm, Work& wk, LeafFn&& leaf) {
     if (S.n == 1) {
         leaf(0);
         return;
     }
     const float ix = 1.0f / vx, iy = 1.0f / vy, iz = 1.0f / vz;
-    int sp = 0, node = 0;
+    int sp = 0, node = 0, cnt = 0;
+    bool trav = true;
+    // one wave-uniform loop: a node step for every lane that still
+    // traverses and has room in its queue; when no lane can step, the
+    // queues are drained
     for (;;) {
+        bool step = trav && cnt <= CQ - 2;
+        if (!__any(step)) {
+            for (int k = 0; k < cnt; ++k) leaf(lm.cand[k * TR_THREADS]);
+            cnt = 0;
+            if (!__any(trav)) break;
+            continue;
+        }
+        if (!step) continue;
         const TNode* nd = S.nodes + node;
         if (COUNT) ++wk.nodes;
         uint32_t c = nd->cells;
-        bool hl = (c & 0xffffu & cells) && slab_hit(nd->lbox, ox, oy, oz, ix, iy, iz, ta, tb);
-        bool hr = ((c >> 16) & cells) && slab_hit(nd->rbox, ox, oy, oz, ix, iy, iz, ta, tb);
+        float tbn = tb;
+        float el = (c & 0xffffu & cells) ? slab_enter(nd->lbox, ox, oy, oz, ix, iy, iz, ta, tbn) : INFINITY;
+        float er = ((c >> 16) & cells) ? slab_enter(nd->rbox, ox, oy, oz, ix, iy, iz, ta, tbn) : INFINITY;
         int lc = nd->lchild, rc = nd->rchild;
-        if (hl && lc < 0) {
-            leaf(~lc);
-            hl = false;
+        if (el < INFINITY && lc < 0) {
+            lm.cand[cnt * TR_THREADS] = ~lc;
+            ++cnt;
+            el = INFINITY;
         }
-        if (hr && rc < 0) {
-            leaf(~rc);
-            hr = false;
+        if (er < INFINITY && rc < 0) {
+            lm.cand[cnt * TR_THREADS] = ~rc;
+            ++cnt;
+            er = INFINITY;
         }
-        if (hl && hr) {
-            stk[sp * TR_THREADS] = rc;
+        if (el < INFINITY && er < INFINITY) {
+            bool lfirst = el <= er;
+            lm.push(sp, lfirst ? rc : lc);
             ++sp;
+            node = lfirst ? lc : rc;
+        } else if (el < INFINITY) {
             node = lc;
-        } else if (hl) {
-            node = lc;
-        } else if (hr) {
+        } else if (er < INFINITY) {
             node = rc;
+        } else if (sp == 0) {
+            trav = false;
         } else {
-            if (sp == 0) break;
             --sp;
-            node = stk[sp * TR_THREADS];
+            node = lm.pop(sp);
         }
     }
 }
@@ -252,165 +338,217 @@ static __device__ __forceinline__ bool clip_box(const SceneView& S, float ox, fl
     return t0 < t1;
 }
 
-template <bool COUNT>
-static __device__ void pass_majorant(const SceneView& S, const MaskView& M, const CellW& cw, float ox, float oy,
-                                     float oz, float vx, float vy, float vz, float ta, float tb, const Lane& L,
-                                     Work& wk) {
-    for (int k = 0; k < TB_BINS; ++k) L.bins[k * TR_THREADS] = 0.0f;
-    const float inv_dt = TB_BINS / (tb - ta), dt = (tb - ta) / TB_BINS;
-    lane_traverse<COUNT>(S, cw.cells, ox, oy, oz, vx, vy, vz, ta, tb, L.stk, wk, [&](int j) {
-        PrimF P = load_prim(S.prims, j);
-        if (COUNT) ++wk.prims;
-        float wgt = cw.mw[P.cell];
-        if (wgt == 0.0f) return;
-        if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
-        ChordF C;
-        if (!chord_f32(P, S.r2, ox, oy, oz, vx, vy, vz, ta, tb, C)) return;
-        float peak = wgt * fabsf(P.amp) * 0.79788456080286535588f * 1.0001f;  // rho w |alpha| c
-        int k0 = max(0, min(TB_BINS - 1, (int)floorf((C.ci - ta) * inv_dt)));
-        int k1 = max(0, min(TB_BINS - 1, (int)floorf((C.co - ta) * inv_dt)));
-        for (int k = k0; k <= k1; ++k) {
-            float blo = ta + k * dt, bhi = blo + dt;
-            float du = fminf(fmaxf(C.tc, blo), bhi) - C.tc;
-            // shrink the minimum slightly so float32 rounding never raises it
-            float m = (C.h2 + C.n2 * du * du) * 0.999f;
-            L.bins[k * TR_THREADS] += peak * __expf(-0.5f * m);
-        }
-    });
+static __device__ __forceinline__ bool prim_on(const MaskView& M, int orig) {
+    return !M.prim_bits || ((M.prim_bits[orig >> 5] >> (orig & 31)) & 1u);
 }
 
-// density at the np points (sorted, within [pa, pb]) into L.pk
-template <bool COUNT>
-static __device__ void pass_density(const SceneView& S, const MaskView& M, const CellW& cw, float ox, float oy,
-                                    float oz, float vx, float vy, float vz, int np, const Lane& L, Work& wk) {
-    float pa = L.pt[0], pb = L.pt[(np - 1) * TR_THREADS];
-    for (int k = 0; k < np; ++k) L.pk[k * TR_THREADS] = 0.0f;
-    lane_traverse<COUNT>(S, cw.cells, ox, oy, oz, vx, vy, vz, pa, pb, L.stk, wk, [&](int j) {
-        PrimF P = load_prim(S.prims, j);
-        if (COUNT) ++wk.prims;
-        float wgt = cw.w[P.cell];
-        if (wgt == 0.0f) return;
-        if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
-        ChordF C;
-        if (!chord_f32(P, S.r2, ox, oy, oz, vx, vy, vz, pa, pb, C, true)) return;
-        float amp = wgt * P.amp * 0.79788456080286535588f;
-        for (int k = 0; k < np; ++k) {
-            float t = L.pt[k * TR_THREADS];
-            if (t < C.ci || t > C.co) continue;
-            float x = ox + t * vx, y = oy + t * vy, z = oz + t * vz;
-            float dx = x - P.mux, dy = y - P.muy, dz = z - P.muz;
-            float m = dx * (P.a00 * dx + P.a01 * dy + P.a02 * dz) + dy * (P.a01 * dx + P.a11 * dy + P.a12 * dz) +
-                      dz * (P.a02 * dx + P.a12 * dy + P.a22 * dz);
-            if (!(m < S.r2)) continue;
-            float ph = P.fx * dx + P.fy * dy + P.fz * dz + P.phi * (float)GF_INV_2PI;
-            float sn, cs;
-            sincos2pi(ph - rintf(ph), &sn, &cs);
-            L.pk[k * TR_THREADS] += amp * __expf(-0.5f * m) * cs;
+// the largest tentative distance held (and its slot)
+static __device__ __forceinline__ float latest_point(const LaneMem& lm, int* slot) {
+    float best = -INFINITY;
+    int ks = 0;
+    for (int k = 0; k < TK; ++k) {
+        float t = lm.t[k * TR_THREADS];
+        if (t > best) {
+            best = t;
+            ks = k;
         }
-    });
-}
-
-// Draws the next round of tentative points from the binned majorant,
-// continuing from (t, bin).  Returns the number of points (0 when the
-// segment is exhausted).  The process restarts at each bin boundary
-// (memoryless).
-static __device__ __forceinline__ int draw_points(float ta, float tb, const Lane& L, float& t, int& bin, Rng& g) {
-    const float dt = (tb - ta) / TB_BINS;
-    int np = 0;
-    while (bin < TB_BINS && np < TB_PTS) {
-        float kb = L.bins[bin * TR_THREADS];
-        float bend = bin == TB_BINS - 1 ? tb : ta + (bin + 1) * dt;
-        if (!(kb > 0.0f)) {
-            t = bend;
-            ++bin;
-            continue;
-        }
-        float tn = t - __logf(g.u()) / kb;
-        if (tn >= bend) {
-            t = bend;
-            ++bin;
-            continue;
-        }
-        t = fmaxf(tn, nextafterf(t, INFINITY));  // strict progress in float32
-        L.pt[np * TR_THREADS] = t;
-        L.pm[np * TR_THREADS] = kb;
-        ++np;
     }
+    *slot = ks;
+    return best;
+}
+
+// One segment window [ta, tb] of the ray o + t v.
+struct Seg {
+    float ox, oy, oz, vx, vy, vz, ta, tb;
+};
+
+// Proposal pass: the window's tentative points into lm.t / lm.xi.  Returns
+// their number; *tcut is the end of the window (tb, or the last point held
+// when the buffer filled up).  The random numbers of a chord come from its
+// own counter-based stream (segment key; primitive, window, proposal), so
+// the points do not depend on the order in which chords are visited.
+template <bool COUNT>
+static __device__ int propose(const SceneView& S, const MaskView& M, const CellW& cw, const Seg& sg, uint32_t k0,
+                              uint32_t k1, int win, const LaneMem& lm, float* tcut_out, Work& wk) {
+    int np = 0;
+    float tcut = sg.tb;
+    lane_traverse<COUNT>(S, cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, tcut, lm, wk, [&](int j) {
+        PrimF P = load_prim(S.prims, j);
+        if (COUNT) ++wk.prims;
+        float mw = cw.mw(P.cell);
+        if (mw == 0.0f || !prim_on(M, P.orig)) return;
+        ChordF C;
+        if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, tcut, C, false)) return;
+        float lam = mw * fabsf(P.amp) * GF_NORM * __expf(-0.5f * C.h2);
+        if (!(lam > 0.0f)) return;
+        float inv = 1.0f / lam;
+        float t = C.ci;
+        for (uint32_t blk = 0;; ++blk) {
+            uint4 r = philox4x32(make_uint4((uint32_t)P.orig, (uint32_t)win, blk, 0x50524f50u), k0, k1);
+            // strict progress in float32 even when the gap rounds away
+            t = fmaxf(t - __logf(unit_float(r.x)) * inv, nextafterf(t, INFINITY));
+            if (!(t < fminf(C.co, tcut))) break;
+            float dt = t - C.tc;
+            if (unit_float(r.y) >= __expf(-0.5f * C.n2 * dt * dt)) continue;  // thinning to the envelope
+            float x = unit_float(r.z);
+            if (COUNT) ++wk.tent;
+            if (np < TK) {
+                lm.t[np * TR_THREADS] = t;
+                lm.xi(np) = x;
+                ++np;
+                if (np == TK) {
+                    int ks;
+                    tcut = latest_point(lm, &ks);
+                }
+            } else {
+                // full: the new point replaces the latest one
+                int ks;
+                latest_point(lm, &ks);
+                lm.t[ks * TR_THREADS] = t;
+                lm.xi(ks) = x;
+                tcut = latest_point(lm, &ks);
+            }
+        }
+    });
+    *tcut_out = tcut;
     return np;
 }
 
-// Ratio tracking over [t0, t1]: T = prod (1 - kappa / kbar).
+// Evaluation pass: kappa (density weights) and mu (majorant weights) at the
+// np points of the window, from every chord that contains them.
 template <bool COUNT>
-static __device__ float ratio_track(const SceneView& S, const MaskView& M, const CellW& cw, float ox, float oy,
-                                    float oz, float vx, float vy, float vz, float t0, float t1, Rng& g, const Lane& L,
-                                    Work& wk) {
-    float ta = t0, tb = t1;
-    if (!clip_box(S, ox, oy, oz, vx, vy, vz, ta, tb)) return 1.0f;
-    pass_majorant<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, ta, tb, L, wk);
-    float T = 1.0f, t = ta;
-    int bin = 0;
-    for (int drawn = 0; drawn < TB_MAX_TENT;) {
-        int np = draw_points(ta, tb, L, t, bin, g);
-        if (np == 0) break;
-        drawn += np;
-        if (COUNT) wk.tent += np;
-        pass_density<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, np, L, wk);
-        for (int k = 0; k < np; ++k) T *= 1.0f - L.pk[k * TR_THREADS] / L.pm[k * TR_THREADS];
+static __device__ void evaluate(const SceneView& S, const MaskView& M, const CellW& cw, const Seg& sg, int np,
+                                const LaneMem& lm, Work& wk) {
+    float pa = INFINITY, pb = -INFINITY;
+    for (int k = 0; k < np; ++k) {
+        float t = lm.t[k * TR_THREADS];
+        pa = fminf(pa, t);
+        pb = fmaxf(pb, t);
+        lm.kap(k) = 0.0f;
+        lm.maj(k) = 0.0f;
     }
-    return T;
+    lane_traverse<COUNT>(S, cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, lm, wk, [&](int j) {
+        PrimF P = load_prim(S.prims, j);
+        if (COUNT) ++wk.prims;
+        float mw = cw.mw(P.cell);
+        if (mw == 0.0f || !prim_on(M, P.orig)) return;
+        ChordF C;
+        if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, C, true)) return;
+        // |rho alpha c| and the signed density weight; kappa and mu take the
+        // same rounded envelope term so that kappa <= mu holds exactly where
+        // the carrier is 1 (a positive density is then tracked with unit
+        // weights)
+        float am = P.amp * GF_NORM, aa = fabsf(am);
+        float ws = copysignf(cw.w(P.cell), am);
+        for (int k = 0; k < np; ++k) {
+            float t = lm.t[k * TR_THREADS];
+            if (t < C.ci || t > C.co) continue;
+            float dt = t - C.tc;
+            float e = __expf(-0.5f * (C.h2 + C.n2 * dt * dt));
+            float dx = sg.ox + t * sg.vx - P.mux, dy = sg.oy + t * sg.vy - P.muy, dz = sg.oz + t * sg.vz - P.muz;
+            float ph = P.fx * dx + P.fy * dy + P.fz * dz + P.phi * (float)GF_INV_2PI;
+            float sn, cs;
+            sincos2pi(ph - rintf(ph), &sn, &cs);
+            float ce = aa * e;
+            lm.kap(k) += ws * (ce * cs);
+            lm.maj(k) += mw * ce;
+        }
+    });
 }
 
-// Weighted delta tracking over [t0, t1] (null-collision form with signed
-// collision weights; Woodcock tracking wherever 0 <= kappa <= kbar).
-// Returns true on a real collision at *tc.
+// Signed-weight delta tracking at one tentative point: real with probability
+// |kappa| / (|kappa| + |mu - kappa|), weight factor sign(kappa) D / mu on a
+// real collision and sign(mu - kappa) D / mu on a null one (D the sum of the
+// two magnitudes).  Woodcock tracking, with unit factors, when 0 <= kappa <= mu.
+static __device__ __forceinline__ bool delta_real(float kap, float mu, float xi, float* fac_real, float* fac_null) {
+    if (kap >= 0.0f && kap <= mu) {
+        *fac_real = *fac_null = 1.0f;
+        return xi * mu < kap;
+    }
+    float kn = mu - kap, D = fabsf(kap) + fabsf(kn);
+    *fac_real = copysignf(D / mu, kap);
+    *fac_null = copysignf(D / mu, kn);
+    return xi * D < fabsf(kap);
+}
+
+#define MODE_RATIO 1
+#define MODE_DELTA 2
+
+// State of the segment a lane is tracking.
+struct SegState {
+    Seg sg;
+    CellW cw;
+    int mode, win;
+    bool live;    // window left to track
+    float T;      // ratio-tracking product
+    float wf;     // delta-tracking weight factor
+    float tc;     // delta collision distance (INFINITY: none)
+    uint32_t k0, k1;  // key of the segment's chord streams
+};
+
+static __device__ __forceinline__ void begin_segment(const SceneView& S, SegState& st, const float* o,
+                                                     const float* v, float t0, float t1, const CellW& cw, int mode,
+                                                     Rng& g) {
+    st.k0 = g.bits();
+    st.k1 = g.bits();
+    st.sg.ox = o[0];
+    st.sg.oy = o[1];
+    st.sg.oz = o[2];
+    st.sg.vx = v[0];
+    st.sg.vy = v[1];
+    st.sg.vz = v[2];
+    st.sg.ta = t0;
+    st.sg.tb = t1;
+    st.live = clip_box(S, o[0], o[1], o[2], v[0], v[1], v[2], st.sg.ta, st.sg.tb);
+    st.cw = cw;
+    st.mode = mode;
+    st.win = 0;
+    st.T = 1.0f;
+    st.wf = 1.0f;
+    st.tc = INFINITY;
+}
+
+// One window of a segment: proposals, evaluation, decisions.  Returns true
+// when the segment is finished.
 template <bool COUNT>
-static __device__ bool delta_track(const SceneView& S, const MaskView& M, const CellW& cw, float ox, float oy,
-                                   float oz, float vx, float vy, float vz, float t0, float t1, Rng& g, float* w,
-                                   float* tc, const Lane& L, Work& wk) {
-    float ta = t0, tb = t1;
-    if (!clip_box(S, ox, oy, oz, vx, vy, vz, ta, tb)) return false;
-    pass_majorant<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, ta, tb, L, wk);
-    float t = ta;
-    int bin = 0;
-    for (int drawn = 0; drawn < TB_MAX_TENT;) {
-        int np = draw_points(ta, tb, L, t, bin, g);
-        if (np == 0) return false;
-        drawn += np;
-        if (COUNT) wk.tent += np;
-        pass_density<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, np, L, wk);
-        for (int k = 0; k < np; ++k) {
-            float kap = L.pk[k * TR_THREADS], kb = L.pm[k * TR_THREADS];
-            float xi = g.u();
-            if (kap >= 0.0f && kap <= kb) {
-                if (xi * kb < kap) {
-                    *tc = L.pt[k * TR_THREADS];
-                    return true;
+static __device__ bool track_window(const SceneView& S, const MaskView& M, SegState& st, const LaneMem& lm,
+                                    Work& wk) {
+    if (!st.live) return true;
+    if (COUNT) ++wk.windows;
+    float tcut;
+    int np = propose<COUNT>(S, M, st.cw, st.sg, st.k0, st.k1, st.win, lm, &tcut, wk);
+    if (np > 0) {
+        evaluate<COUNT>(S, M, st.cw, st.sg, np, lm, wk);
+        if (st.mode & MODE_RATIO)
+            for (int k = 0; k < np; ++k) st.T *= 1.0f - lm.kap(k) / lm.maj(k);
+        if ((st.mode & MODE_DELTA) && !(st.tc < INFINITY)) {
+            // the collision is the earliest real point; null factors of the
+            // points before it apply
+            float tbest = INFINITY, freal = 1.0f, fr, fn;
+            for (int k = 0; k < np; ++k) {
+                float t = lm.t[k * TR_THREADS];
+                if (t < tbest && delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn)) {
+                    tbest = t;
+                    freal = fr;
                 }
-            } else {
-                float kn = kb - kap;
-                float Dn = fabsf(kap) + fabsf(kn);
-                if (xi * Dn < fabsf(kap)) {
-                    *w *= copysignf(Dn / kb, kap);
-                    *tc = L.pt[k * TR_THREADS];
-                    return true;
-                }
-                *w *= copysignf(Dn / kb, kn);
             }
+            float w = freal;
+            for (int k = 0; k < np; ++k) {
+                float t = lm.t[k * TR_THREADS];
+                if (t < tbest) {
+                    delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn);
+                    w *= fn;
+                }
+            }
+            st.wf *= w;
+            st.tc = tbest;
         }
     }
-    return false;
+    bool full = tcut < st.sg.tb;
+    bool stop = !full || (st.mode == MODE_DELTA && st.tc < INFINITY) || ++st.win >= MAX_WINDOWS;
+    if (!stop) st.sg.ta = tcut;
+    return stop;
 }
-
-// per-lane LDS of a TR_THREADS-wide block
-#define LANE_LDS                                                               \
-    __shared__ int stk_all[TR_STACK * TR_THREADS];                             \
-    __shared__ float fl_all[(TB_BINS + 3 * TB_PTS) * TR_THREADS];              \
-    Lane L;                                                                    \
-    L.stk = stk_all + threadIdx.x;                                             \
-    L.bins = fl_all + threadIdx.x;                                             \
-    L.pt = fl_all + TB_BINS * TR_THREADS + threadIdx.x;                        \
-    L.pm = fl_all + (TB_BINS + TB_PTS) * TR_THREADS + threadIdx.x;             \
-    L.pk = fl_all + (TB_BINS + 2 * TB_PTS) * TR_THREADS + threadIdx.x;
 
 static __device__ __forceinline__ void sample_sphere(Rng& g, float* d) {
     float u1 = g.u(), u2 = g.u();
@@ -457,9 +595,120 @@ static __device__ __forceinline__ int ray_of_tr(int gid, int n, int tile_w) {
     return py < height ? py * tile_w + px : -1;
 }
 
-static __device__ __forceinline__ int64_t tr_threads(int n, int tile_w) {
+static int64_t tr_threads(int64_t n, int tile_w) {
     if (tile_w <= 0) return n;
     return (int64_t)(tile_w / 8) * ((n / tile_w + 7) / 8) * 64;
+}
+
+// ---------------------------------------------------------------------------
+// per-ray drivers
+// ---------------------------------------------------------------------------
+struct RenderArgs {
+    int spp, multiple, max_scatter, stochastic;
+    float albedo, hg, env;
+    uint64_t seed;
+};
+
+// Ratio-tracking transmittance of the ray over [tmin, tmax], spp samples.
+template <bool COUNT>
+static __device__ void ratio_ray(const SceneView& S, const MaskView& M, const float* r, uint32_t key, int spp,
+                                 uint64_t seed, const LaneMem& lm, float* Tmean, float* Tvar, Work& wk) {
+    const CellW fixed = fixed_weights(M);
+    float s1 = 0.0f, s2 = 0.0f;
+    int s = 0;
+    Rng g;
+    g.init(seed, key, 0u, 1u);
+    SegState st;
+    begin_segment(S, st, r, r + 3, r[6], r[7], fixed, MODE_RATIO, g);
+    while (s < spp) {
+        if (!track_window<COUNT>(S, M, st, lm, wk)) continue;
+        s1 += st.T;
+        s2 += st.T * st.T;
+        if (++s < spp) {
+            g.init(seed, key, (uint32_t)s, 1u);
+            begin_segment(S, st, r, r + 3, r[6], r[7], fixed, MODE_RATIO, g);
+        }
+    }
+    *Tmean = s1 / spp;
+    *Tvar = spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 / spp) / (spp - 1)) : 0.0f;
+}
+
+// Radiance of one camera ray, spp samples, with a constant environment.
+// Single scattering: the primary segment is delta-tracked (and ratio-tracked
+// for its transmittance on the same tentative points); a real collision
+// scatters isotropically and ratio-tracks the way out.  Multiple scattering:
+// delta tracking from segment to segment with Henyey-Greenstein scattering
+// until escape or max_scatter scatterings.
+template <bool COUNT>
+static __device__ void render_ray(const SceneView& S, const MaskView& M, const RenderArgs& A, const float* r,
+                                  uint32_t key, const LaneMem& lm, float* out4, Work& wk) {
+    const CellW fixed = fixed_weights(M);
+    float s1 = 0.0f, s2 = 0.0f, q1 = 0.0f, q2 = 0.0f;
+    float w = 1.0f, L = 0.0f, Tp = 1.0f;
+    int nsc = 0, seg = 0, s = 0;
+    bool shadow = false;
+    Rng g;
+    SegState st;
+    auto start_sample = [&]() {
+        g.init(A.seed, key, (uint32_t)s, 0u);
+        w = 1.0f;
+        L = 0.0f;
+        Tp = 1.0f;
+        nsc = seg = 0;
+        shadow = false;
+        CellW cw = A.stochastic ? stochastic_weights(S, r[3], r[4], r[5], g) : fixed;
+        begin_segment(S, st, r, r + 3, r[6], r[7], cw, MODE_RATIO | MODE_DELTA, g);
+    };
+    auto end_sample = [&]() {
+        s1 += L;
+        s2 += L * L;
+        q1 += Tp;
+        q2 += Tp * Tp;
+        if (++s < A.spp) start_sample();
+    };
+    start_sample();
+    while (s < A.spp) {
+        if (!track_window<COUNT>(S, M, st, lm, wk)) continue;
+        if (seg == 0) Tp = st.T;
+        if (shadow) {
+            L += w * A.albedo * st.T * A.env;
+            end_sample();
+            continue;
+        }
+        w *= st.wf;
+        if (!(st.tc < INFINITY)) {
+            L += w * A.env;
+            end_sample();
+            continue;
+        }
+        float x[3] = {st.sg.ox + st.tc * st.sg.vx, st.sg.oy + st.tc * st.sg.vy, st.sg.oz + st.tc * st.sg.vz};
+        float d[3];
+        int mode;
+        if (!A.multiple) {
+            sample_sphere(g, d);
+            shadow = true;
+            mode = MODE_RATIO;
+        } else {
+            if (nsc >= A.max_scatter) {
+                end_sample();
+                continue;
+            }
+            ++nsc;
+            w *= A.albedo;
+            float vn = rsqrtf(st.sg.vx * st.sg.vx + st.sg.vy * st.sg.vy + st.sg.vz * st.sg.vz);
+            float wi[3] = {st.sg.vx * vn, st.sg.vy * vn, st.sg.vz * vn};
+            sample_hg(g, A.hg, wi, d);
+            mode = MODE_DELTA;
+        }
+        ++seg;
+        CellW cw = A.stochastic ? stochastic_weights(S, d[0], d[1], d[2], g) : fixed;
+        begin_segment(S, st, x, d, 0.0f, INFINITY, cw, mode, g);
+    }
+    float inv = 1.0f / A.spp;
+    out4[0] = s1 * inv;
+    out4[1] = A.spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 * inv) / (A.spp - 1)) : 0.0f;
+    out4[2] = q1 * inv;
+    out4[3] = A.spp > 1 ? fmaxf(0.0f, (q2 - q1 * q1 * inv) / (A.spp - 1)) : 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -470,8 +719,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_density(SceneView S, MaskView M,
     __shared__ int stk[TR_STACK * TR_THREADS];
     int i = blockIdx.x * TR_THREADS + threadIdx.x;
     if (i >= n) return;
-    CellW cw;
-    fixed_weights(M, cw);
+    CellW cw = fixed_weights(M);
     float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
     Work wk{};
     kappa[i] = point_density<false>(S, M, cw, x, y, z, stk + threadIdx.x, wk);
@@ -481,120 +729,56 @@ __global__ __launch_bounds__(TR_THREADS) void k_density(SceneView S, MaskView M,
             int ix = min(S.G - 1, max(0, (int)floorf((x - S.glo[0]) * S.ginv[0])));
             int iy = min(S.G - 1, max(0, (int)floorf((y - S.glo[1]) * S.ginv[1])));
             int iz = min(S.G - 1, max(0, (int)floorf((z - S.glo[2]) * S.ginv[2])));
-            kb = voxel_majorant(S, (iz * S.G + iy) * S.G + ix, cw.mw);
+            float mw[GF_NCELLS];
+            for (int c = 0; c < GF_NCELLS; ++c) mw[c] = cw.mw(c);
+            kb = voxel_majorant(S, (iz * S.G + iy) * S.G + ix, mw);
         }
         kbar[i] = kb;
     }
 }
 
 __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, const float* __restrict__ rays, int n,
-                                                      int tile_w, int spp, uint64_t seed, float* __restrict__ Tm,
+                                                      int tile_w, unsigned nblocks, int spp, uint64_t seed,
+                                                      float* __restrict__ ws, float* __restrict__ Tm,
                                                       float* __restrict__ Tv) {
-    LANE_LDS
-    int gid = blockIdx.x * TR_THREADS + threadIdx.x;
-    int idx = ray_of_tr(gid, n, tile_w);
-    if (idx < 0) return;
-    const float* r = rays + (size_t)idx * 8;
-    CellW cw;
-    fixed_weights(M, cw);
-    float s1 = 0.0f, s2 = 0.0f;
-    Work wk{};
-    for (int s = 0; s < spp; ++s) {
-        Rng g;
-        g.init(seed, (uint32_t)idx, (uint32_t)s, 1u);
-        float T = ratio_track<false>(S, M, cw, r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], g, L, wk);
-        s1 += T;
-        s2 += T * T;
+    LANE_MEM(ws)
+    for (unsigned b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        int idx = ray_of_tr((int)(b * TR_THREADS + threadIdx.x), n, tile_w);
+        if (idx < 0) continue;
+        float a, v;
+        Work wk{};
+        ratio_ray<false>(S, M, rays + (size_t)idx * 8, (uint32_t)idx, spp, seed, lm, &a, &v, wk);
+        Tm[idx] = a;
+        if (Tv) Tv[idx] = v;
     }
-    Tm[idx] = s1 / spp;
-    if (Tv) Tv[idx] = spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 / spp) / (spp - 1)) : 0.0f;
-}
-
-struct RenderArgs {
-    int spp, multiple, max_scatter, stochastic;
-    float albedo, hg, env;
-    uint64_t seed;
-};
-
-// All samples of one ray; random streams keyed by (seed, key, sample).
-template <bool COUNT>
-static __device__ void render_ray(const SceneView& S, const MaskView& M, const RenderArgs& A, const float* r,
-                                  uint32_t key, const Lane& ln, float* Lmean, float* Lvar, float* Tmean, float* Tvar,
-                                  Work& wk) {
-    CellW fixed;
-    fixed_weights(M, fixed);
-    float s1 = 0.0f, s2 = 0.0f, q1 = 0.0f, q2 = 0.0f;
-    for (int s = 0; s < A.spp; ++s) {
-        Rng g, gT;
-        g.init(A.seed, key, (uint32_t)s, 0u);
-        gT.init(A.seed, key, (uint32_t)s, 1u);
-        float ox = r[0], oy = r[1], oz = r[2], vx = r[3], vy = r[4], vz = r[5], t0 = r[6], t1 = r[7];
-        float w = 1.0f, L = 0.0f, Tp = 1.0f;
-        int nsc = 0;
-        for (int seg = 0;; ++seg) {
-            CellW cw = fixed;
-            if (A.stochastic) stochastic_weights(S, vx, vy, vz, g, cw);
-            if (seg == 0) Tp = ratio_track<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, t0, t1, gT, ln, wk);
-            float tc;
-            if (!delta_track<COUNT>(S, M, cw, ox, oy, oz, vx, vy, vz, t0, t1, g, &w, &tc, ln, wk)) {
-                L += w * A.env;
-                break;
-            }
-            float x = ox + tc * vx, y = oy + tc * vy, z = oz + tc * vz;
-            if (!A.multiple) {
-                float d[3];
-                sample_sphere(g, d);
-                L += w * A.albedo *
-                     ratio_track<COUNT>(S, M, cw, x, y, z, d[0], d[1], d[2], 0.0f, INFINITY, g, ln, wk) * A.env;
-                break;
-            }
-            if (nsc >= A.max_scatter) break;
-            ++nsc;
-            w *= A.albedo;
-            float vn = rsqrtf(vx * vx + vy * vy + vz * vz);
-            float wi[3] = {vx * vn, vy * vn, vz * vn}, wo[3];
-            sample_hg(g, A.hg, wi, wo);
-            ox = x; oy = y; oz = z;
-            vx = wo[0]; vy = wo[1]; vz = wo[2];
-            t0 = 0.0f;
-            t1 = INFINITY;
-        }
-        s1 += L;
-        s2 += L * L;
-        q1 += Tp;
-        q2 += Tp * Tp;
-    }
-    float inv = 1.0f / A.spp;
-    *Lmean = s1 * inv;
-    *Lvar = A.spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 * inv) / (A.spp - 1)) : 0.0f;
-    *Tmean = q1 * inv;
-    *Tvar = A.spp > 1 ? fmaxf(0.0f, (q2 - q1 * q1 * inv) / (A.spp - 1)) : 0.0f;
 }
 
 template <bool COUNT>
 __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, const float* __restrict__ rays, int n,
-                                                       int tile_w, RenderArgs A, float* __restrict__ Lm,
+                                                       int tile_w, unsigned nblocks, RenderArgs A,
+                                                       float* __restrict__ ws, float* __restrict__ Lm,
                                                        float* __restrict__ Lv, float* __restrict__ Tm,
                                                        float* __restrict__ Tv,
                                                        unsigned long long* __restrict__ counters) {
-    LANE_LDS
-    int gid = blockIdx.x * TR_THREADS + threadIdx.x;
-    int idx = ray_of_tr(gid, n, tile_w);
-    if (idx < 0) return;
-    float a, b, c, d;
+    LANE_MEM(ws)
     Work wk{};
-    render_ray<COUNT>(S, M, A, rays + (size_t)idx * 8, (uint32_t)idx, L, &a, &b, &c, &d, wk);
+    for (unsigned b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        int idx = ray_of_tr((int)(b * TR_THREADS + threadIdx.x), n, tile_w);
+        if (idx < 0) continue;
+        float o[4];
+        render_ray<COUNT>(S, M, A, rays + (size_t)idx * 8, (uint32_t)idx, lm, o, wk);
+        if (COUNT) continue;
+        Lm[idx] = o[0];
+        if (Lv) Lv[idx] = o[1];
+        if (Tm) Tm[idx] = o[2];
+        if (Tv) Tv[idx] = o[3];
+    }
     if (COUNT) {
         atomicAdd(counters + 0, wk.tent);
         atomicAdd(counters + 1, wk.nodes);
         atomicAdd(counters + 2, wk.prims);
-        atomicAdd(counters + 3, wk.voxels);
-        return;
+        atomicAdd(counters + 3, wk.windows);
     }
-    Lm[idx] = a;
-    if (Lv) Lv[idx] = b;
-    if (Tm) Tm[idx] = c;
-    if (Tv) Tv[idx] = d;
 }
 
 // Serving: one launch renders tiles of many requests (each tile a contiguous
@@ -614,17 +798,33 @@ struct ServeTile {
 };
 
 __global__ __launch_bounds__(TR_THREADS) void k_render_tiles(const ServeReq* __restrict__ reqs,
-                                                             const ServeTile* __restrict__ tiles, int blocks_per_tile) {
-    LANE_LDS
-    const ServeTile tl = tiles[blockIdx.x / blocks_per_tile];
-    int local = (blockIdx.x % blocks_per_tile) * TR_THREADS + threadIdx.x;
-    if (local >= tl.count) return;
-    const ServeReq& R = reqs[tl.req];
-    int idx = tl.first + local;
-    float a, b, c, d;
-    Work wk{};
-    render_ray<false>(R.S, R.M, R.A, R.rays + (size_t)idx * 8, (uint32_t)idx, L, &a, &b, &c, &d, wk);
-    R.out[idx] = a;
+                                                             const ServeTile* __restrict__ tiles, unsigned nblocks,
+                                                             int blocks_per_tile, float* __restrict__ ws) {
+    LANE_MEM(ws)
+    for (unsigned b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const ServeTile tl = tiles[b / blocks_per_tile];
+        int local = (int)(b % blocks_per_tile) * TR_THREADS + threadIdx.x;
+        if (local >= tl.count) continue;
+        const ServeReq& R = reqs[tl.req];
+        int idx = tl.first + local;
+        float o[4];
+        Work wk{};
+        render_ray<false>(R.S, R.M, R.A, R.rays + (size_t)idx * 8, (uint32_t)idx, lm, o, wk);
+        R.out[idx] = o[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// workspace: WS_ROWS x TR_THREADS floats per resident wave
+// ---------------------------------------------------------------------------
+static unsigned res_blocks(int64_t nblocks) { return (unsigned)std::min<int64_t>(nblocks, TR_RES_BLOCKS); }
+
+size_t gf_track_workspace_bytes(int64_t nblocks) {
+    return (size_t)res_blocks(nblocks) * WS_ROWS * TR_THREADS * sizeof(float);
+}
+
+static unsigned tr_blocks(int64_t n, int tile_w) {
+    return (unsigned)((tr_threads(n, tile_w) + TR_THREADS - 1) / TR_THREADS);
 }
 
 gf_status gf_serve_fill_req(const gf_request* q, const float* rays, void* out_desc) {
@@ -649,10 +849,17 @@ size_t gf_serve_req_size() { return sizeof(ServeReq); }
 size_t gf_serve_tile_size() { return sizeof(ServeTile); }
 int gf_serve_tile_threads() { return TR_THREADS; }
 
-gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int tile_rays, hipStream_t sm) {
+size_t gf_serve_workspace_bytes(int max_tiles, int tile_rays) {
+    int64_t bpt = (tile_rays + TR_THREADS - 1) / TR_THREADS;
+    return gf_track_workspace_bytes((int64_t)max_tiles * bpt);
+}
+
+gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int tile_rays, float* ws,
+                          hipStream_t sm) {
     int bpt = (tile_rays + TR_THREADS - 1) / TR_THREADS;
-    k_render_tiles<<<(unsigned)(ntiles * bpt), TR_THREADS, 0, sm>>>((const ServeReq*)dreqs, (const ServeTile*)dtiles,
-                                                                    bpt);
+    unsigned nb = (unsigned)(ntiles * bpt);
+    k_render_tiles<<<res_blocks(nb), TR_THREADS, 0, sm>>>((const ServeReq*)dreqs, (const ServeTile*)dtiles, nb, bpt,
+                                                          ws);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }
@@ -697,10 +904,25 @@ static gf_status check_depth(const gf_scene_s* s, const char* who) {
     return GF_OK;
 }
 
-static unsigned tr_blocks(int64_t n, int tile_w) {
-    int64_t t = tile_w <= 0 ? n : (int64_t)(tile_w / 8) * ((n / tile_w + 7) / 8) * 64;
-    return (unsigned)((t + TR_THREADS - 1) / TR_THREADS);
-}
+// Stream-ordered workspace of one launch (freed on the same stream after it).
+struct Workspace {
+    float* p = nullptr;
+    hipStream_t sm = nullptr;
+    gf_status alloc(int64_t nblocks, hipStream_t s, const char* who) {
+        sm = s;
+        size_t bytes = gf_track_workspace_bytes(nblocks);
+        hipError_t e = hipMallocAsync((void**)&p, bytes, sm);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return gf_fail(GF_ENOMEM, "%s: workspace of %zu bytes: %s", who, bytes, hipGetErrorString(e));
+        }
+        return GF_OK;
+    }
+    ~Workspace() {
+        if (p) (void)hipFreeAsync(p, sm);
+    }
+};
 
 static gf_status check_rays_tr(int64_t n, int tile_w, const char* who) {
     if (n < 0 || n > (int64_t)INT32_MAX / 8) return gf_fail(GF_EINVAL, "%s: ray count out of range", who);
@@ -728,8 +950,12 @@ extern "C" gf_status gf_transmittance_ratio(gf_scene s, const float* rays, int64
     gf_status st = check_rays_tr(n, image_width, "gf_transmittance_ratio");
     if (st == GF_OK) st = check_depth(s, "gf_transmittance_ratio");
     if (st != GF_OK || n == 0) return st;
-    k_ratio<<<tr_blocks(n, image_width), TR_THREADS, 0, (hipStream_t)stream>>>(
-        gf_scene_view(s), gf_mask_view(mask), rays, (int)n, image_width, spp, seed, T_mean, T_var);
+    unsigned nb = tr_blocks(n, image_width);
+    Workspace ws;
+    st = ws.alloc(nb, (hipStream_t)stream, "gf_transmittance_ratio");
+    if (st != GF_OK) return st;
+    k_ratio<<<res_blocks(nb), TR_THREADS, 0, (hipStream_t)stream>>>(gf_scene_view(s), gf_mask_view(mask), rays, (int)n,
+                                                                    image_width, nb, spp, seed, ws.p, T_mean, T_var);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }
@@ -746,14 +972,18 @@ gf_status gf_render_launch(gf_scene s, const float* rays, int64_t n, int image_w
     A.hg = d->hg_g;
     A.env = d->env;
     A.seed = d->seed;
+    unsigned nb = tr_blocks(n, image_width);
+    Workspace ws;
+    gf_status st = ws.alloc(nb, sm, "gf_render");
+    if (st != GF_OK) return st;
     if (counters)
-        k_render<true><<<tr_blocks(n, image_width), TR_THREADS, 0, sm>>>(
-            gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n, image_width, A, nullptr, nullptr, nullptr, nullptr,
-            counters);
+        k_render<true><<<res_blocks(nb), TR_THREADS, 0, sm>>>(gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n,
+                                                              image_width, nb, A, ws.p, nullptr, nullptr, nullptr,
+                                                              nullptr, counters);
     else
-        k_render<false><<<tr_blocks(n, image_width), TR_THREADS, 0, sm>>>(
-            gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n, image_width, A, L_mean, L_var, T_mean, T_var,
-            nullptr);
+        k_render<false><<<res_blocks(nb), TR_THREADS, 0, sm>>>(gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n,
+                                                               image_width, nb, A, ws.p, L_mean, L_var, T_mean, T_var,
+                                                               nullptr);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }
