@@ -37,17 +37,23 @@ PEAK_HBM_GBS = 8000.0
 RAY_BYTES, OUT_BYTES, PRIM_BYTES, NODE_BYTES, VISIT_BYTES = 32, 8, 60, 32, 64
 
 
+def log(*a):
+    """progress on stderr (the JSON result alone goes to stdout)"""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="blob100k")
     ap.add_argument("--spp", type=int, default=8)
-    ap.add_argument("--render", action="store_true", help="include the single-scattering render in every step")
+    ap.add_argument("--no-render", dest="render", action="store_false",
+                    help="leave the single-scattering render out of the step (optical depth only)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-requests", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -114,17 +120,21 @@ def main():
             record.append((e0, e1, evs))
         return scene, bits
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         scene, bits = step(None)
         scene.close()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log("warmup step %d done" % k)
     rec = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         scene, bits = step(rec)
         scene.close()
+        # progress only; the GPU work of the steps stays queued back to back
+        log("step %d queued" % k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log("timed steps done: %.1f ms per step" % (1e3 * (t1 - t0) / args.steps))
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     for e0, e1, evs in rec:
         timings["build"].append(e0.elapsed_time(e1))
@@ -141,7 +151,8 @@ def main():
     scene = gf.Scene(params, rho)
     masks, bits = masks_for(scene)
     tau_bytes, ren_bytes = [], []
-    for m in masks:
+    for k, m in enumerate(masks):
+        log("counting work of mask %s" % mask_names[k])
         nodes, hits = gf.gf_optical_depth_counts(scene, rays, m, image_width=width)
         nn, nh = int(nodes.sum().item()), int(hits.sum().item())
         tau_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + PRIM_BYTES * nh + NODE_BYTES * nn)
@@ -180,8 +191,10 @@ def main():
     }
 
     if not args.no_serving:
+        log("serving trace")
         result["serving"] = serving(args, gf, W, np, torch)
     if not args.no_cpu:
+        log("oracle on the host")
         result["cpu_baseline"] = cpu_baseline(args, np, params_h, rays_h, rho, tau_ms, ren_ms, npix, units,
                                               ms_per_step)
     scene.close()
@@ -216,16 +229,19 @@ def serving(args, gf, W, np, torch):
     n = args.serving_requests
     reqs = gen.serving_requests(n, seed=5)
     # warm both paths
-    serve.run_plain(scenes, reqs[:4], np.zeros(4))
+    serve.run_plain(scenes, reqs[:1], np.zeros(1))
     # saturation throughput of the plain renderer on this trace decides the rate
     t0 = time.perf_counter()
-    serve.run_plain(scenes, reqs[:24], np.zeros(24))
-    plain_rate = 24 / (time.perf_counter() - t0)
+    serve.run_plain(scenes, reqs[:3], np.zeros(3))
+    plain_rate = 3 / (time.perf_counter() - t0)
     qps = 0.7 * plain_rate
     arrivals = gen.poisson_arrivals(n, qps, seed=6)
+    log("serving: plain renderer saturates at %.3f requests/s; replaying %d requests at %.3f/s" % (plain_rate, n, qps))
     lat_s, mk_s, _, held = serve.run_server(scenes, reqs, arrivals, mem_budget=1 << 30, tile_rays=4096,
                                             max_tiles=96, time_limit=600)
+    log("serving: continuous batching done in %.1f s" % mk_s)
     lat_p, mk_p, _ = serve.run_plain(scenes, reqs, arrivals, time_limit=600)
+    log("serving: plain renderer done in %.1f s" % mk_p)
     out = {"qps": round(qps, 2), "requests": n, "scenes": W.SERVE_SCENES,
            "continuous_batching": serve.summarize(lat_s, mk_s, reqs),
            "plain_per_request": serve.summarize(lat_p, mk_p, reqs), "max_bytes_held": held}

@@ -46,14 +46,21 @@
 #define MAX_WINDOWS 4096
 // Waves resident in one launch: each owns a workspace slice, and loops over
 // the launch's tiles with a grid stride.
-#define TR_RES_BLOCKS 4096
+#define TR_RES_BLOCKS 3072
+// Chords a lane records while proposing a window; the evaluation pass reads
+// them back instead of walking the LBVH again (a window with more chords is
+// evaluated by a second traversal).
+#define CL 1024
 
 // Workspace rows of a wave (each row: TR_THREADS lanes x 4 B).
 #define WS_KAP 0
 #define WS_MAJ TK
 #define WS_XI (2 * TK)
 #define WS_SPILL (3 * TK)
-#define WS_ROWS (3 * TK + TR_STACK - TS_LDS)
+#define WS_CJ (WS_SPILL + TR_STACK - TS_LDS)
+#define WS_CI (WS_CJ + CL)
+#define WS_CO (WS_CI + CL)
+#define WS_ROWS (WS_CO + CL)
 
 // c_i / amp_i: the density's normalisation (2 pi)^-3/2 / (s0 s1 s2) over the
 // optical-depth amplitude 1 / (4 pi s0 s1 s2), i.e. sqrt(2 / pi)
@@ -193,6 +200,9 @@ struct LaneMem {
     __device__ float& kap(int k) const { return ws[(WS_KAP + k) * TR_THREADS]; }
     __device__ float& maj(int k) const { return ws[(WS_MAJ + k) * TR_THREADS]; }
     __device__ float& xi(int k) const { return ws[(WS_XI + k) * TR_THREADS]; }
+    __device__ int& cj(int e) const { return ((int*)ws)[(WS_CJ + e) * TR_THREADS]; }
+    __device__ float& ci(int e) const { return ws[(WS_CI + e) * TR_THREADS]; }
+    __device__ float& co(int e) const { return ws[(WS_CO + e) * TR_THREADS]; }
     __device__ void push(int sp, int v) const {
         if (sp < TS_LDS)
             stk[sp * TR_THREADS] = v;
@@ -362,70 +372,136 @@ struct Seg {
     float ox, oy, oz, vx, vy, vz, ta, tb;
 };
 
-// Proposal pass: the window's tentative points into lm.t / lm.xi.  Returns
-// their number; *tcut is the end of the window (tb, or the last point held
-// when the buffer filled up).  The random numbers of a chord come from its
-// own counter-based stream (segment key; primitive, window, proposal), so
-// the points do not depend on the order in which chords are visited.
+// Proposal state of a window: points held, chords recorded, window end
+// (the segment end, or the last point held once the buffer is full).
+struct Prop {
+    int np, nc;
+    float tcut;
+};
+
+// Proposal work of one leaf j: records its chord and draws its tentative
+// points into lm.t / lm.xi.  The random numbers of a chord come from its own
+// counter-based stream (segment key; primitive, window, proposal), so the
+// points do not depend on the order in which chords are visited.
 template <bool COUNT>
-static __device__ int propose(const SceneView& S, const MaskView& M, const CellW& cw, const Seg& sg, uint32_t k0,
-                              uint32_t k1, int win, const LaneMem& lm, float* tcut_out, Work& wk) {
-    int np = 0;
-    float tcut = sg.tb;
-    lane_traverse<COUNT>(S, cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, tcut, lm, wk, [&](int j) {
-        PrimF P = load_prim(S.prims, j);
-        if (COUNT) ++wk.prims;
-        float mw = cw.mw(P.cell);
-        if (mw == 0.0f || !prim_on(M, P.orig)) return;
-        ChordF C;
-        if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, tcut, C, false)) return;
-        float lam = mw * fabsf(P.amp) * GF_NORM * __expf(-0.5f * C.h2);
-        if (!(lam > 0.0f)) return;
-        float inv = 1.0f / lam;
-        float t = C.ci;
-        for (uint32_t blk = 0;; ++blk) {
-            uint4 r = philox4x32(make_uint4((uint32_t)P.orig, (uint32_t)win, blk, 0x50524f50u), k0, k1);
-            // strict progress in float32 even when the gap rounds away
-            t = fmaxf(t - __logf(unit_float(r.x)) * inv, nextafterf(t, INFINITY));
-            if (!(t < fminf(C.co, tcut))) break;
-            float dt = t - C.tc;
-            if (unit_float(r.y) >= __expf(-0.5f * C.n2 * dt * dt)) continue;  // thinning to the envelope
-            float x = unit_float(r.z);
-            if (COUNT) ++wk.tent;
-            if (np < TK) {
-                lm.t[np * TR_THREADS] = t;
-                lm.xi(np) = x;
-                ++np;
-                if (np == TK) {
-                    int ks;
-                    tcut = latest_point(lm, &ks);
-                }
-            } else {
-                // full: the new point replaces the latest one
-                int ks;
-                latest_point(lm, &ks);
-                lm.t[ks * TR_THREADS] = t;
-                lm.xi(ks) = x;
-                tcut = latest_point(lm, &ks);
-            }
+static __device__ void prop_leaf(const SceneView& S, const MaskView& M, const CellW& cw, const Seg& sg, uint32_t k0,
+                                 uint32_t k1, int win, int j, Prop& pr, const LaneMem& lm, Work& wk) {
+    PrimF P = load_prim(S.prims, j);
+    if (COUNT) ++wk.prims;
+    float mw = cw.mw(P.cell);
+    if (mw == 0.0f || !prim_on(M, P.orig)) return;
+    ChordF C;
+    if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, pr.tcut, C, false)) return;
+    if (pr.nc < CL) {
+        lm.cj(pr.nc) = j;
+        lm.ci(pr.nc) = C.ci;
+        lm.co(pr.nc) = C.co;
+    }
+    ++pr.nc;
+    float lam = mw * fabsf(P.amp) * GF_NORM * __expf(-0.5f * C.h2);
+    if (!(lam > 0.0f)) return;
+    float inv = 1.0f / lam;
+    float t = C.ci;
+    for (uint32_t blk = 0;; ++blk) {
+        uint4 r = philox4x32(make_uint4((uint32_t)P.orig, (uint32_t)win, blk, 0x50524f50u), k0, k1);
+        // strict progress in float32 even when the gap rounds away
+        t = fmaxf(t - __logf(unit_float(r.x)) * inv, nextafterf(t, INFINITY));
+        if (!(t < fminf(C.co, pr.tcut))) break;
+        float dt = t - C.tc;
+        if (unit_float(r.y) >= __expf(-0.5f * C.n2 * dt * dt)) continue;  // thinning to the envelope
+        float x = unit_float(r.z);
+        if (COUNT) ++wk.tent;
+        int ks;
+        if (pr.np < TK) {
+            lm.t[pr.np * TR_THREADS] = t;
+            lm.xi(pr.np) = x;
+            ++pr.np;
+            if (pr.np == TK) pr.tcut = latest_point(lm, &ks);
+        } else {
+            // full: the new point replaces the latest one
+            latest_point(lm, &ks);
+            lm.t[ks * TR_THREADS] = t;
+            lm.xi(ks) = x;
+            pr.tcut = latest_point(lm, &ks);
         }
-    });
-    *tcut_out = tcut;
-    return np;
+    }
+}
+
+// points in ascending order (the evaluation looks them up by bisection)
+static __device__ void sort_points(const LaneMem& lm, int np) {
+    for (int a = 1; a < np; ++a) {
+        float tv = lm.t[a * TR_THREADS], xv = lm.xi(a);
+        int b = a - 1;
+        while (b >= 0 && lm.t[b * TR_THREADS] > tv) {
+            lm.t[(b + 1) * TR_THREADS] = lm.t[b * TR_THREADS];
+            lm.xi(b + 1) = lm.xi(b);
+            --b;
+        }
+        lm.t[(b + 1) * TR_THREADS] = tv;
+        lm.xi(b + 1) = xv;
+    }
+}
+
+// kappa and mu contributions of primitive P (chord C) to the window's
+// sorted points t[k0..] inside the chord.  kappa and mu take the same
+// rounded envelope term, so kappa <= mu holds exactly where the carrier is 1
+// (a positive density is then tracked with unit weights).
+static __device__ __forceinline__ void add_chord(const PrimF& P, const ChordF& C, const CellW& cw, float mw,
+                                                 const Seg& sg, int np, int k, const LaneMem& lm) {
+    float am = P.amp * GF_NORM, aa = fabsf(am);
+    float ws = copysignf(cw.w(P.cell), am);
+    for (; k < np; ++k) {
+        float t = lm.t[k * TR_THREADS];
+        if (t > C.co) break;
+        float dt = t - C.tc;
+        float e = __expf(-0.5f * (C.h2 + C.n2 * dt * dt));
+        float dx = sg.ox + t * sg.vx - P.mux, dy = sg.oy + t * sg.vy - P.muy, dz = sg.oz + t * sg.vz - P.muz;
+        float ph = P.fx * dx + P.fy * dy + P.fz * dz + P.phi * (float)GF_INV_2PI;
+        float sn, cs;
+        sincos2pi(ph - rintf(ph), &sn, &cs);
+        float ce = aa * e;
+        lm.kap(k) += ws * (ce * cs);
+        lm.maj(k) += mw * ce;
+    }
+}
+
+// first point (ascending) at or after t
+static __device__ __forceinline__ int first_point(const LaneMem& lm, int np, float t) {
+    int lo = 0, hi = np;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (lm.t[mid * TR_THREADS] < t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
 }
 
 // Evaluation pass: kappa (density weights) and mu (majorant weights) at the
-// np points of the window, from every chord that contains them.
+// np sorted points of the window, from every chord that contains them: the
+// chords recorded by the proposal pass, or a second traversal when there
+// were more than CL of them.
 template <bool COUNT>
 static __device__ void evaluate(const SceneView& S, const MaskView& M, const CellW& cw, const Seg& sg, int np,
-                                const LaneMem& lm, Work& wk) {
-    float pa = INFINITY, pb = -INFINITY;
+                                int nchords, const LaneMem& lm, Work& wk) {
     for (int k = 0; k < np; ++k) {
-        float t = lm.t[k * TR_THREADS];
-        pa = fminf(pa, t);
-        pb = fmaxf(pb, t);
         lm.kap(k) = 0.0f;
         lm.maj(k) = 0.0f;
+    }
+    const float pa = lm.t[0], pb = lm.t[(np - 1) * TR_THREADS];
+    if (nchords <= CL) {
+        for (int e = 0; e < nchords; ++e) {
+            float ci = lm.ci(e), co = lm.co(e);
+            int k = first_point(lm, np, ci);
+            if (k == np || lm.t[k * TR_THREADS] > co) continue;
+            PrimF P = load_prim(S.prims, lm.cj(e));
+            if (COUNT) ++wk.prims;
+            ChordF C;
+            if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, C, true)) continue;
+            add_chord(P, C, cw, cw.mw(P.cell), sg, np, first_point(lm, np, C.ci), lm);
+        }
+        return;
     }
     lane_traverse<COUNT>(S, cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, lm, wk, [&](int j) {
         PrimF P = load_prim(S.prims, j);
@@ -434,25 +510,7 @@ static __device__ void evaluate(const SceneView& S, const MaskView& M, const Cel
         if (mw == 0.0f || !prim_on(M, P.orig)) return;
         ChordF C;
         if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, C, true)) return;
-        // |rho alpha c| and the signed density weight; kappa and mu take the
-        // same rounded envelope term so that kappa <= mu holds exactly where
-        // the carrier is 1 (a positive density is then tracked with unit
-        // weights)
-        float am = P.amp * GF_NORM, aa = fabsf(am);
-        float ws = copysignf(cw.w(P.cell), am);
-        for (int k = 0; k < np; ++k) {
-            float t = lm.t[k * TR_THREADS];
-            if (t < C.ci || t > C.co) continue;
-            float dt = t - C.tc;
-            float e = __expf(-0.5f * (C.h2 + C.n2 * dt * dt));
-            float dx = sg.ox + t * sg.vx - P.mux, dy = sg.oy + t * sg.vy - P.muy, dz = sg.oz + t * sg.vz - P.muz;
-            float ph = P.fx * dx + P.fy * dy + P.fz * dz + P.phi * (float)GF_INV_2PI;
-            float sn, cs;
-            sincos2pi(ph - rintf(ph), &sn, &cs);
-            float ce = aa * e;
-            lm.kap(k) += ws * (ce * cs);
-            lm.maj(k) += mw * ce;
-        }
+        add_chord(P, C, cw, mw, sg, np, first_point(lm, np, C.ci), lm);
     });
 }
 
@@ -508,45 +566,101 @@ static __device__ __forceinline__ void begin_segment(const SceneView& S, SegStat
     st.tc = INFINITY;
 }
 
-// One window of a segment: proposals, evaluation, decisions.  Returns true
-// when the segment is finished.
+// Resumable proposal traversal of a lane's window (front to back over
+// [ta, tcut]; leaves are queued in lm.cand for a converged drain).
+struct Trav {
+    int node, sp, cnt;
+    bool on;  // nodes left to visit
+};
+
+static __device__ __forceinline__ void begin_window(const SceneView& S, const SegState& st, Trav& tr, Prop& pr,
+                                                    const LaneMem& lm) {
+    pr.np = 0;
+    pr.nc = 0;
+    pr.tcut = st.sg.tb;
+    tr.node = 0;
+    tr.sp = 0;
+    tr.cnt = 0;
+    tr.on = st.live;
+    if (st.live && S.n == 1) {  // the root is the only leaf
+        lm.cand[0] = 0;
+        tr.cnt = 1;
+        tr.on = false;
+    }
+}
+
 template <bool COUNT>
-static __device__ bool track_window(const SceneView& S, const MaskView& M, SegState& st, const LaneMem& lm,
-                                    Work& wk) {
+static __device__ __forceinline__ void node_step(const SceneView& S, const SegState& st, float tcut, Trav& tr,
+                                                 const LaneMem& lm, Work& wk) {
+    const Seg& sg = st.sg;
+    const float ix = 1.0f / sg.vx, iy = 1.0f / sg.vy, iz = 1.0f / sg.vz;
+    const TNode* nd = S.nodes + tr.node;
+    if (COUNT) ++wk.nodes;
+    uint32_t c = nd->cells;
+    float el = (c & 0xffffu & st.cw.cells) ? slab_enter(nd->lbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, sg.ta, tcut)
+                                           : INFINITY;
+    float er = ((c >> 16) & st.cw.cells) ? slab_enter(nd->rbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, sg.ta, tcut)
+                                         : INFINITY;
+    int lc = nd->lchild, rc = nd->rchild;
+    if (el < INFINITY && lc < 0) {
+        lm.cand[tr.cnt * TR_THREADS] = ~lc;
+        ++tr.cnt;
+        el = INFINITY;
+    }
+    if (er < INFINITY && rc < 0) {
+        lm.cand[tr.cnt * TR_THREADS] = ~rc;
+        ++tr.cnt;
+        er = INFINITY;
+    }
+    if (el < INFINITY && er < INFINITY) {
+        bool lfirst = el <= er;
+        lm.push(tr.sp, lfirst ? rc : lc);
+        ++tr.sp;
+        tr.node = lfirst ? lc : rc;
+    } else if (el < INFINITY) {
+        tr.node = lc;
+    } else if (er < INFINITY) {
+        tr.node = rc;
+    } else if (tr.sp == 0) {
+        tr.on = false;
+    } else {
+        --tr.sp;
+        tr.node = lm.pop(tr.sp);
+    }
+}
+
+// After the proposal traversal: evaluation and decisions of the window.
+// Returns true when the segment is finished.
+template <bool COUNT>
+static __device__ bool close_window(const SceneView& S, const MaskView& M, SegState& st, const Prop& pr,
+                                    const LaneMem& lm, Work& wk) {
     if (!st.live) return true;
     if (COUNT) ++wk.windows;
-    float tcut;
-    int np = propose<COUNT>(S, M, st.cw, st.sg, st.k0, st.k1, st.win, lm, &tcut, wk);
+    const int np = pr.np;
     if (np > 0) {
-        evaluate<COUNT>(S, M, st.cw, st.sg, np, lm, wk);
+        sort_points(lm, np);
+        evaluate<COUNT>(S, M, st.cw, st.sg, np, pr.nc, lm, wk);
         if (st.mode & MODE_RATIO)
             for (int k = 0; k < np; ++k) st.T *= 1.0f - lm.kap(k) / lm.maj(k);
         if ((st.mode & MODE_DELTA) && !(st.tc < INFINITY)) {
             // the collision is the earliest real point; null factors of the
             // points before it apply
-            float tbest = INFINITY, freal = 1.0f, fr, fn;
+            float w = 1.0f, fr, fn;
             for (int k = 0; k < np; ++k) {
-                float t = lm.t[k * TR_THREADS];
-                if (t < tbest && delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn)) {
-                    tbest = t;
-                    freal = fr;
+                bool real = delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn);
+                if (real) {
+                    w *= fr;
+                    st.tc = lm.t[k * TR_THREADS];
+                    break;
                 }
-            }
-            float w = freal;
-            for (int k = 0; k < np; ++k) {
-                float t = lm.t[k * TR_THREADS];
-                if (t < tbest) {
-                    delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn);
-                    w *= fn;
-                }
+                w *= fn;
             }
             st.wf *= w;
-            st.tc = tbest;
         }
     }
-    bool full = tcut < st.sg.tb;
+    bool full = pr.tcut < st.sg.tb;
     bool stop = !full || (st.mode == MODE_DELTA && st.tc < INFINITY) || ++st.win >= MAX_WINDOWS;
-    if (!stop) st.sg.ta = tcut;
+    if (!stop) st.sg.ta = pr.tcut;
     return stop;
 }
 
@@ -601,7 +715,7 @@ static int64_t tr_threads(int64_t n, int tile_w) {
 }
 
 // ---------------------------------------------------------------------------
-// per-ray drivers
+// per-ray drivers: resumable per-lane state, advanced one window at a time
 // ---------------------------------------------------------------------------
 struct RenderArgs {
     int spp, multiple, max_scatter, stochastic;
@@ -610,28 +724,35 @@ struct RenderArgs {
 };
 
 // Ratio-tracking transmittance of the ray over [tmin, tmax], spp samples.
-template <bool COUNT>
-static __device__ void ratio_ray(const SceneView& S, const MaskView& M, const float* r, uint32_t key, int spp,
-                                 uint64_t seed, const LaneMem& lm, float* Tmean, float* Tvar, Work& wk) {
-    const CellW fixed = fixed_weights(M);
-    float s1 = 0.0f, s2 = 0.0f;
-    int s = 0;
+struct RatioLane {
+    const float* r;
+    uint32_t key;
+    int s;
+    float s1, s2;
     Rng g;
-    g.init(seed, key, 0u, 1u);
     SegState st;
-    begin_segment(S, st, r, r + 3, r[6], r[7], fixed, MODE_RATIO, g);
-    while (s < spp) {
-        if (!track_window<COUNT>(S, M, st, lm, wk)) continue;
+    __device__ void begin(const SceneView& S, const MaskView& M, const float* ray, uint32_t k, uint64_t seed) {
+        r = ray;
+        key = k;
+        s = 0;
+        s1 = s2 = 0.0f;
+        start(S, M, seed);
+    }
+    __device__ void start(const SceneView& S, const MaskView& M, uint64_t seed) {
+        g.init(seed, key, (uint32_t)s, 1u);
+        begin_segment(S, st, r, r + 3, r[6], r[7], fixed_weights(M), MODE_RATIO, g);
+    }
+    // the segment (one sample) is finished; true once all samples are done
+    __device__ bool segment_done(const SceneView& S, const MaskView& M, int spp, uint64_t seed) {
         s1 += st.T;
         s2 += st.T * st.T;
         if (++s < spp) {
-            g.init(seed, key, (uint32_t)s, 1u);
-            begin_segment(S, st, r, r + 3, r[6], r[7], fixed, MODE_RATIO, g);
+            start(S, M, seed);
+            return false;
         }
+        return true;
     }
-    *Tmean = s1 / spp;
-    *Tvar = spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 / spp) / (spp - 1)) : 0.0f;
-}
+};
 
 // Radiance of one camera ray, spp samples, with a constant environment.
 // Single scattering: the primary segment is delta-tracked (and ratio-tracked
@@ -639,47 +760,56 @@ static __device__ void ratio_ray(const SceneView& S, const MaskView& M, const fl
 // scatters isotropically and ratio-tracks the way out.  Multiple scattering:
 // delta tracking from segment to segment with Henyey-Greenstein scattering
 // until escape or max_scatter scatterings.
-template <bool COUNT>
-static __device__ void render_ray(const SceneView& S, const MaskView& M, const RenderArgs& A, const float* r,
-                                  uint32_t key, const LaneMem& lm, float* out4, Work& wk) {
-    const CellW fixed = fixed_weights(M);
-    float s1 = 0.0f, s2 = 0.0f, q1 = 0.0f, q2 = 0.0f;
-    float w = 1.0f, L = 0.0f, Tp = 1.0f;
-    int nsc = 0, seg = 0, s = 0;
-    bool shadow = false;
+struct RenderLane {
+    const float* r;
+    uint32_t key;
+    int s, nsc, seg;
+    bool shadow;
+    float w, L, Tp;
+    float s1, s2, q1, q2;
     Rng g;
     SegState st;
-    auto start_sample = [&]() {
+    __device__ void begin(const SceneView& S, const MaskView& M, const RenderArgs& A, const float* ray, uint32_t k) {
+        r = ray;
+        key = k;
+        s = 0;
+        s1 = s2 = q1 = q2 = 0.0f;
+        start(S, M, A);
+    }
+    __device__ void start(const SceneView& S, const MaskView& M, const RenderArgs& A) {
         g.init(A.seed, key, (uint32_t)s, 0u);
         w = 1.0f;
         L = 0.0f;
         Tp = 1.0f;
         nsc = seg = 0;
         shadow = false;
-        CellW cw = A.stochastic ? stochastic_weights(S, r[3], r[4], r[5], g) : fixed;
+        CellW cw = A.stochastic ? stochastic_weights(S, r[3], r[4], r[5], g) : fixed_weights(M);
         begin_segment(S, st, r, r + 3, r[6], r[7], cw, MODE_RATIO | MODE_DELTA, g);
-    };
-    auto end_sample = [&]() {
+    }
+    // closes the current sample; true when it was the last one
+    __device__ bool end_sample(const SceneView& S, const MaskView& M, const RenderArgs& A) {
         s1 += L;
         s2 += L * L;
         q1 += Tp;
         q2 += Tp * Tp;
-        if (++s < A.spp) start_sample();
-    };
-    start_sample();
-    while (s < A.spp) {
-        if (!track_window<COUNT>(S, M, st, lm, wk)) continue;
+        if (++s < A.spp) {
+            start(S, M, A);
+            return false;
+        }
+        return true;
+    }
+    // the current segment is finished: scatter, escape or close the sample;
+    // true once all samples are done
+    __device__ bool segment_done(const SceneView& S, const MaskView& M, const RenderArgs& A) {
         if (seg == 0) Tp = st.T;
         if (shadow) {
             L += w * A.albedo * st.T * A.env;
-            end_sample();
-            continue;
+            return end_sample(S, M, A);
         }
         w *= st.wf;
         if (!(st.tc < INFINITY)) {
             L += w * A.env;
-            end_sample();
-            continue;
+            return end_sample(S, M, A);
         }
         float x[3] = {st.sg.ox + st.tc * st.sg.vx, st.sg.oy + st.tc * st.sg.vy, st.sg.oz + st.tc * st.sg.vz};
         float d[3];
@@ -689,10 +819,7 @@ static __device__ void render_ray(const SceneView& S, const MaskView& M, const R
             shadow = true;
             mode = MODE_RATIO;
         } else {
-            if (nsc >= A.max_scatter) {
-                end_sample();
-                continue;
-            }
+            if (nsc >= A.max_scatter) return end_sample(S, M, A);
             ++nsc;
             w *= A.albedo;
             float vn = rsqrtf(st.sg.vx * st.sg.vx + st.sg.vy * st.sg.vy + st.sg.vz * st.sg.vz);
@@ -701,15 +828,112 @@ static __device__ void render_ray(const SceneView& S, const MaskView& M, const R
             mode = MODE_DELTA;
         }
         ++seg;
-        CellW cw = A.stochastic ? stochastic_weights(S, d[0], d[1], d[2], g) : fixed;
+        CellW cw = A.stochastic ? stochastic_weights(S, d[0], d[1], d[2], g) : fixed_weights(M);
         begin_segment(S, st, x, d, 0.0f, INFINITY, cw, mode, g);
+        return false;
     }
-    float inv = 1.0f / A.spp;
-    out4[0] = s1 * inv;
-    out4[1] = A.spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 * inv) / (A.spp - 1)) : 0.0f;
-    out4[2] = q1 * inv;
-    out4[3] = A.spp > 1 ? fmaxf(0.0f, (q2 - q1 * q1 * inv) / (A.spp - 1)) : 0.0f;
+    __device__ void result(const RenderArgs& A, float* out4) const {
+        float inv = 1.0f / A.spp;
+        out4[0] = s1 * inv;
+        out4[1] = A.spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 * inv) / (A.spp - 1)) : 0.0f;
+        out4[2] = q1 * inv;
+        out4[3] = A.spp > 1 ? fmaxf(0.0f, (q2 - q1 * q1 * inv) / (A.spp - 1)) : 0.0f;
+    }
+};
+
+// Work distribution: the rays of a launch are numbered 0..total-1 and handed
+// out by a launch-wide counter to lanes as they become free (one atomic per
+// wave and refill), so every lane stays busy until the work runs out and no
+// wave waits on another's tiles.  Returns this lane's new item (or total when
+// the work is exhausted); lanes with need == false get -1.
+static __device__ __forceinline__ int fetch_item(unsigned* counter, bool need, int total) {
+    uint64_t m = __ballot(need);
+    int cnt = __popcll(m);
+    int leader = __ffsll((long long)m) - 1;
+    unsigned base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (unsigned)cnt);
+    base = __shfl(base, leader);
+    if (!need) return -1;
+    unsigned it = base + (unsigned)__popcll(m & lanemask_lt());
+    return it < (unsigned)total ? (int)it : total;
 }
+
+// Lanes run below this many node steps at once before the wave drains
+// the leaf queues, and this many lanes wait with a finished traversal before
+// the wave closes their windows: the heavy leaf and window work then runs
+// with most lanes taking part.
+#define DRAIN_BELOW 16
+#define CLOSE_AT 48
+
+// Persistent loop of one wave.  Each lane advances its own window: node
+// steps, leaf drains and window closes are interleaved per lane, so a lane
+// never waits for the longest traversal of its wave; a finished window opens
+// the next one (next window, segment, sample, or a new ray from the
+// counter).  `map(item)` gives the ray index of an item (-1: none),
+// `begin(idx)` starts a ray, `seg()` is its current segment,
+// `segment_done()` moves past a finished segment (true when the ray is
+// complete) and `done(idx)` writes its result.
+template <bool COUNT, class Ctx, class Map, class Begin, class SegRef, class SegDone, class Done>
+static __device__ __forceinline__ void run_lanes(unsigned* counter, int total, const LaneMem& lm, Work& wk, Ctx&& ctx,
+                                                 Map&& map, Begin&& begin, SegRef&& seg, SegDone&& segment_done,
+                                                 Done&& done) {
+    int idx = -1;
+    bool more = true;
+    Trav tr;
+    Prop pr;
+    tr.on = false;
+    tr.cnt = 0;
+    for (;;) {
+        bool need = idx < 0 && more;
+        if (__any(need)) {
+            int it = fetch_item(counter, need, total);
+            if (need) {
+                if (it >= total) {
+                    more = false;
+                } else {
+                    idx = map(it);
+                    if (idx >= 0) {
+                        begin(idx);
+                        begin_window(ctx.S(), seg(), tr, pr, lm);
+                    }
+                }
+            }
+        }
+        const bool act = idx >= 0;
+        if (!__any(act || more)) break;
+        // node steps
+        if (act && tr.on && tr.cnt <= CQ - 2) node_step<COUNT>(ctx.S(), seg(), pr.tcut, tr, lm, wk);
+        // leaf drains
+        if (__popcll(__ballot(act && tr.on && tr.cnt <= CQ - 2)) < DRAIN_BELOW && act) {
+            SegState& st = seg();
+            for (int k = 0; k < tr.cnt; ++k)
+                prop_leaf<COUNT>(ctx.S(), ctx.M(), st.cw, st.sg, st.k0, st.k1, st.win, lm.cand[k * TR_THREADS], pr,
+                                 lm, wk);
+            tr.cnt = 0;
+        }
+        // window closes
+        const bool pend = act && !tr.on && tr.cnt == 0;
+        const int npend = __popcll(__ballot(pend));
+        if (npend >= CLOSE_AT || (npend > 0 && npend == __popcll(__ballot(act)))) {
+            if (pend) {
+                if (close_window<COUNT>(ctx.S(), ctx.M(), seg(), pr, lm, wk) && segment_done()) {
+                    done(idx);
+                    idx = -1;
+                } else {
+                    begin_window(ctx.S(), seg(), tr, pr, lm);
+                }
+            }
+        }
+    }
+}
+
+// scene and mask of a launch
+struct LaunchCtx {
+    const SceneView& s;
+    const MaskView& m;
+    __device__ const SceneView& S() const { return s; }
+    __device__ const MaskView& M() const { return m; }
+};
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -737,42 +961,51 @@ __global__ __launch_bounds__(TR_THREADS) void k_density(SceneView S, MaskView M,
     }
 }
 
+// The first 256 B of the workspace hold the launch's item counter (zeroed by
+// k_zero before the launch); the lanes' slices follow.
+#define WS_HEAD 64
+
+__global__ void k_zero(unsigned* p) { *p = 0u; }
+
 __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, const float* __restrict__ rays, int n,
-                                                      int tile_w, unsigned nblocks, int spp, uint64_t seed,
+                                                      int tile_w, int total, int spp, uint64_t seed,
                                                       float* __restrict__ ws, float* __restrict__ Tm,
                                                       float* __restrict__ Tv) {
-    LANE_MEM(ws)
-    for (unsigned b = blockIdx.x; b < nblocks; b += gridDim.x) {
-        int idx = ray_of_tr((int)(b * TR_THREADS + threadIdx.x), n, tile_w);
-        if (idx < 0) continue;
-        float a, v;
-        Work wk{};
-        ratio_ray<false>(S, M, rays + (size_t)idx * 8, (uint32_t)idx, spp, seed, lm, &a, &v, wk);
-        Tm[idx] = a;
-        if (Tv) Tv[idx] = v;
-    }
+    LANE_MEM(ws + WS_HEAD)
+    RatioLane rl;
+    Work wk{};
+    run_lanes<false>(
+        (unsigned*)ws, total, lm, wk, LaunchCtx{S, M}, [&](int it) { return ray_of_tr(it, n, tile_w); },
+        [&](int idx) { rl.begin(S, M, rays + (size_t)idx * 8, (uint32_t)idx, seed); },
+        [&]() -> SegState& { return rl.st; }, [&]() { return rl.segment_done(S, M, spp, seed); },
+        [&](int idx) {
+            Tm[idx] = rl.s1 / spp;
+            if (Tv) Tv[idx] = spp > 1 ? fmaxf(0.0f, (rl.s2 - rl.s1 * rl.s1 / spp) / (spp - 1)) : 0.0f;
+        });
 }
 
 template <bool COUNT>
 __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, const float* __restrict__ rays, int n,
-                                                       int tile_w, unsigned nblocks, RenderArgs A,
-                                                       float* __restrict__ ws, float* __restrict__ Lm,
-                                                       float* __restrict__ Lv, float* __restrict__ Tm,
-                                                       float* __restrict__ Tv,
+                                                       int tile_w, int total, RenderArgs A, float* __restrict__ ws,
+                                                       float* __restrict__ Lm, float* __restrict__ Lv,
+                                                       float* __restrict__ Tm, float* __restrict__ Tv,
                                                        unsigned long long* __restrict__ counters) {
-    LANE_MEM(ws)
+    LANE_MEM(ws + WS_HEAD)
+    RenderLane rl;
     Work wk{};
-    for (unsigned b = blockIdx.x; b < nblocks; b += gridDim.x) {
-        int idx = ray_of_tr((int)(b * TR_THREADS + threadIdx.x), n, tile_w);
-        if (idx < 0) continue;
-        float o[4];
-        render_ray<COUNT>(S, M, A, rays + (size_t)idx * 8, (uint32_t)idx, lm, o, wk);
-        if (COUNT) continue;
-        Lm[idx] = o[0];
-        if (Lv) Lv[idx] = o[1];
-        if (Tm) Tm[idx] = o[2];
-        if (Tv) Tv[idx] = o[3];
-    }
+    run_lanes<COUNT>(
+        (unsigned*)ws, total, lm, wk, LaunchCtx{S, M}, [&](int it) { return ray_of_tr(it, n, tile_w); },
+        [&](int idx) { rl.begin(S, M, A, rays + (size_t)idx * 8, (uint32_t)idx); },
+        [&]() -> SegState& { return rl.st; }, [&]() { return rl.segment_done(S, M, A); },
+        [&](int idx) {
+            if (COUNT) return;
+            float o[4];
+            rl.result(A, o);
+            Lm[idx] = o[0];
+            if (Lv) Lv[idx] = o[1];
+            if (Tm) Tm[idx] = o[2];
+            if (Tv) Tv[idx] = o[3];
+        });
     if (COUNT) {
         atomicAdd(counters + 0, wk.tent);
         atomicAdd(counters + 1, wk.nodes);
@@ -797,21 +1030,36 @@ struct ServeTile {
     int req, first, count, pad;
 };
 
+// scene and mask of the request of a lane's current ray
+struct ServeCtx {
+    const ServeReq* const& r;
+    __device__ const SceneView& S() const { return r->S; }
+    __device__ const MaskView& M() const { return r->M; }
+};
+
 __global__ __launch_bounds__(TR_THREADS) void k_render_tiles(const ServeReq* __restrict__ reqs,
-                                                             const ServeTile* __restrict__ tiles, unsigned nblocks,
-                                                             int blocks_per_tile, float* __restrict__ ws) {
-    LANE_MEM(ws)
-    for (unsigned b = blockIdx.x; b < nblocks; b += gridDim.x) {
-        const ServeTile tl = tiles[b / blocks_per_tile];
-        int local = (int)(b % blocks_per_tile) * TR_THREADS + threadIdx.x;
-        if (local >= tl.count) continue;
-        const ServeReq& R = reqs[tl.req];
-        int idx = tl.first + local;
-        float o[4];
-        Work wk{};
-        render_ray<false>(R.S, R.M, R.A, R.rays + (size_t)idx * 8, (uint32_t)idx, lm, o, wk);
-        R.out[idx] = o[0];
-    }
+                                                             const ServeTile* __restrict__ tiles, int tile_rays,
+                                                             int total, float* __restrict__ ws) {
+    LANE_MEM(ws + WS_HEAD)
+    RenderLane rl;
+    Work wk{};
+    const ServeReq* R = reqs;
+    run_lanes<false>(
+        (unsigned*)ws, total, lm, wk, ServeCtx{R},
+        [&](int it) {
+            const ServeTile tl = tiles[it / tile_rays];
+            int local = it % tile_rays;
+            if (local >= tl.count) return -1;
+            R = reqs + tl.req;
+            return tl.first + local;
+        },
+        [&](int idx) { rl.begin(R->S, R->M, R->A, R->rays + (size_t)idx * 8, (uint32_t)idx); },
+        [&]() -> SegState& { return rl.st; }, [&]() { return rl.segment_done(R->S, R->M, R->A); },
+        [&](int idx) {
+            float o[4];
+            rl.result(R->A, o);
+            R->out[idx] = o[0];
+        });
 }
 
 // ---------------------------------------------------------------------------
@@ -820,7 +1068,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_render_tiles(const ServeReq* __r
 static unsigned res_blocks(int64_t nblocks) { return (unsigned)std::min<int64_t>(nblocks, TR_RES_BLOCKS); }
 
 size_t gf_track_workspace_bytes(int64_t nblocks) {
-    return (size_t)res_blocks(nblocks) * WS_ROWS * TR_THREADS * sizeof(float);
+    return ((size_t)WS_HEAD + (size_t)res_blocks(nblocks) * WS_ROWS * TR_THREADS) * sizeof(float);
 }
 
 static unsigned tr_blocks(int64_t n, int tile_w) {
@@ -857,9 +1105,9 @@ size_t gf_serve_workspace_bytes(int max_tiles, int tile_rays) {
 gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int tile_rays, float* ws,
                           hipStream_t sm) {
     int bpt = (tile_rays + TR_THREADS - 1) / TR_THREADS;
-    unsigned nb = (unsigned)(ntiles * bpt);
-    k_render_tiles<<<res_blocks(nb), TR_THREADS, 0, sm>>>((const ServeReq*)dreqs, (const ServeTile*)dtiles, nb, bpt,
-                                                          ws);
+    k_zero<<<1, 1, 0, sm>>>((unsigned*)ws);
+    k_render_tiles<<<res_blocks((int64_t)ntiles * bpt), TR_THREADS, 0, sm>>>(
+        (const ServeReq*)dreqs, (const ServeTile*)dtiles, tile_rays, ntiles * tile_rays, ws);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }
@@ -954,8 +1202,10 @@ extern "C" gf_status gf_transmittance_ratio(gf_scene s, const float* rays, int64
     Workspace ws;
     st = ws.alloc(nb, (hipStream_t)stream, "gf_transmittance_ratio");
     if (st != GF_OK) return st;
+    k_zero<<<1, 1, 0, (hipStream_t)stream>>>((unsigned*)ws.p);
     k_ratio<<<res_blocks(nb), TR_THREADS, 0, (hipStream_t)stream>>>(gf_scene_view(s), gf_mask_view(mask), rays, (int)n,
-                                                                    image_width, nb, spp, seed, ws.p, T_mean, T_var);
+                                                                    image_width, (int)tr_threads(n, image_width), spp,
+                                                                    seed, ws.p, T_mean, T_var);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }
@@ -976,14 +1226,16 @@ gf_status gf_render_launch(gf_scene s, const float* rays, int64_t n, int image_w
     Workspace ws;
     gf_status st = ws.alloc(nb, sm, "gf_render");
     if (st != GF_OK) return st;
+    int total = (int)tr_threads(n, image_width);
+    k_zero<<<1, 1, 0, sm>>>((unsigned*)ws.p);
     if (counters)
         k_render<true><<<res_blocks(nb), TR_THREADS, 0, sm>>>(gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n,
-                                                              image_width, nb, A, ws.p, nullptr, nullptr, nullptr,
+                                                              image_width, total, A, ws.p, nullptr, nullptr, nullptr,
                                                               nullptr, counters);
     else
         k_render<false><<<res_blocks(nb), TR_THREADS, 0, sm>>>(gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n,
-                                                               image_width, nb, A, ws.p, L_mean, L_var, T_mean, T_var,
-                                                               nullptr);
+                                                               image_width, total, A, ws.p, L_mean, L_var, T_mean,
+                                                               T_var, nullptr);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }
