@@ -34,7 +34,7 @@
 #define TR_THREADS 64
 #define TR_STACK 64  // deepest LBVH the per-lane traversal supports
 #define TS_LDS 24    // per-lane stack entries kept in LDS; deeper ones go to the workspace
-#define TK 32        // tentative points per window
+#define TK 64        // tentative points per window
 #define CQ 8         // leaf candidates a lane queues before the wave processes them
 // Majorant weight cap of a stochastic cell.  It bounds the work of a path
 // that drew a heavily weighted (rarely drawn) bin; ratio tracking and the
@@ -47,20 +47,13 @@
 // Waves resident in one launch: each owns a workspace slice, and loops over
 // the launch's tiles with a grid stride.
 #define TR_RES_BLOCKS 3072
-// Chords a lane records while proposing a window; the evaluation pass reads
-// them back instead of walking the LBVH again (a window with more chords is
-// evaluated by a second traversal).
-#define CL 1024
 
 // Workspace rows of a wave (each row: TR_THREADS lanes x 4 B).
 #define WS_KAP 0
 #define WS_MAJ TK
 #define WS_XI (2 * TK)
 #define WS_SPILL (3 * TK)
-#define WS_CJ (WS_SPILL + TR_STACK - TS_LDS)
-#define WS_CI (WS_CJ + CL)
-#define WS_CO (WS_CI + CL)
-#define WS_ROWS (WS_CO + CL)
+#define WS_ROWS (WS_SPILL + TR_STACK - TS_LDS)
 
 // c_i / amp_i: the density's normalisation (2 pi)^-3/2 / (s0 s1 s2) over the
 // optical-depth amplitude 1 / (4 pi s0 s1 s2), i.e. sqrt(2 / pi)
@@ -200,9 +193,6 @@ struct LaneMem {
     __device__ float& kap(int k) const { return ws[(WS_KAP + k) * TR_THREADS]; }
     __device__ float& maj(int k) const { return ws[(WS_MAJ + k) * TR_THREADS]; }
     __device__ float& xi(int k) const { return ws[(WS_XI + k) * TR_THREADS]; }
-    __device__ int& cj(int e) const { return ((int*)ws)[(WS_CJ + e) * TR_THREADS]; }
-    __device__ float& ci(int e) const { return ws[(WS_CI + e) * TR_THREADS]; }
-    __device__ float& co(int e) const { return ws[(WS_CO + e) * TR_THREADS]; }
     __device__ void push(int sp, int v) const {
         if (sp < TS_LDS)
             stk[sp * TR_THREADS] = v;
@@ -372,15 +362,15 @@ struct Seg {
     float ox, oy, oz, vx, vy, vz, ta, tb;
 };
 
-// Proposal state of a window: points held, chords recorded, window end
-// (the segment end, or the last point held once the buffer is full).
+// Proposal state of a window: points held and window end (the segment end,
+// or the last point held once the buffer is full).
 struct Prop {
-    int np, nc;
+    int np;
     float tcut;
 };
 
-// Proposal work of one leaf j: records its chord and draws its tentative
-// points into lm.t / lm.xi.  The random numbers of a chord come from its own
+// Proposal work of one leaf j: draws its tentative points into lm.t /
+// lm.xi.  The random numbers of a chord come from its own
 // counter-based stream (segment key; primitive, window, proposal), so the
 // points do not depend on the order in which chords are visited.
 template <bool COUNT>
@@ -392,12 +382,6 @@ static __device__ void prop_leaf(const SceneView& S, const MaskView& M, const Ce
     if (mw == 0.0f || !prim_on(M, P.orig)) return;
     ChordF C;
     if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, pr.tcut, C, false)) return;
-    if (pr.nc < CL) {
-        lm.cj(pr.nc) = j;
-        lm.ci(pr.nc) = C.ci;
-        lm.co(pr.nc) = C.co;
-    }
-    ++pr.nc;
     float lam = mw * fabsf(P.amp) * GF_NORM * __expf(-0.5f * C.h2);
     if (!(lam > 0.0f)) return;
     float inv = 1.0f / lam;
@@ -478,31 +462,13 @@ static __device__ __forceinline__ int first_point(const LaneMem& lm, int np, flo
     return lo;
 }
 
-// Evaluation pass: kappa (density weights) and mu (majorant weights) at the
-// np sorted points of the window, from every chord that contains them: the
-// chords recorded by the proposal pass, or a second traversal when there
-// were more than CL of them.
+// Evaluation pass of a lane's own window: kappa (density weights) and mu
+// (majorant weights) at its np sorted points, from every chord that contains
+// them (a second per-lane traversal over [first point, last point]).
 template <bool COUNT>
 static __device__ void evaluate(const SceneView& S, const MaskView& M, const CellW& cw, const Seg& sg, int np,
-                                int nchords, const LaneMem& lm, Work& wk) {
-    for (int k = 0; k < np; ++k) {
-        lm.kap(k) = 0.0f;
-        lm.maj(k) = 0.0f;
-    }
+                                const LaneMem& lm, Work& wk) {
     const float pa = lm.t[0], pb = lm.t[(np - 1) * TR_THREADS];
-    if (nchords <= CL) {
-        for (int e = 0; e < nchords; ++e) {
-            float ci = lm.ci(e), co = lm.co(e);
-            int k = first_point(lm, np, ci);
-            if (k == np || lm.t[k * TR_THREADS] > co) continue;
-            PrimF P = load_prim(S.prims, lm.cj(e));
-            if (COUNT) ++wk.prims;
-            ChordF C;
-            if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, C, true)) continue;
-            add_chord(P, C, cw, cw.mw(P.cell), sg, np, first_point(lm, np, C.ci), lm);
-        }
-        return;
-    }
     lane_traverse<COUNT>(S, cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, lm, wk, [&](int j) {
         PrimF P = load_prim(S.prims, j);
         if (COUNT) ++wk.prims;
@@ -566,102 +532,133 @@ static __device__ __forceinline__ void begin_segment(const SceneView& S, SegStat
     st.tc = INFINITY;
 }
 
-// Resumable proposal traversal of a lane's window (front to back over
-// [ta, tcut]; leaves are queued in lm.cand for a converged drain).
-struct Trav {
-    int node, sp, cnt;
-    bool on;  // nodes left to visit
-};
-
-static __device__ __forceinline__ void begin_window(const SceneView& S, const SegState& st, Trav& tr, Prop& pr,
-                                                    const LaneMem& lm) {
+static __device__ __forceinline__ void begin_prop(Prop& pr, const SegState& st) {
     pr.np = 0;
-    pr.nc = 0;
     pr.tcut = st.sg.tb;
-    tr.node = 0;
-    tr.sp = 0;
-    tr.cnt = 0;
-    tr.on = st.live;
-    if (st.live && S.n == 1) {  // the root is the only leaf
-        lm.cand[0] = 0;
-        tr.cnt = 1;
-        tr.on = false;
-    }
 }
 
+// Proposal pass of a lane's own window: per-lane LBVH traversal (incoherent
+// secondary rays).
 template <bool COUNT>
-static __device__ __forceinline__ void node_step(const SceneView& S, const SegState& st, float tcut, Trav& tr,
-                                                 const LaneMem& lm, Work& wk) {
-    const Seg& sg = st.sg;
-    const float ix = 1.0f / sg.vx, iy = 1.0f / sg.vy, iz = 1.0f / sg.vz;
-    const TNode* nd = S.nodes + tr.node;
-    if (COUNT) ++wk.nodes;
-    uint32_t c = nd->cells;
-    float el = (c & 0xffffu & st.cw.cells) ? slab_enter(nd->lbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, sg.ta, tcut)
-                                           : INFINITY;
-    float er = ((c >> 16) & st.cw.cells) ? slab_enter(nd->rbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, sg.ta, tcut)
-                                         : INFINITY;
-    int lc = nd->lchild, rc = nd->rchild;
-    if (el < INFINITY && lc < 0) {
-        lm.cand[tr.cnt * TR_THREADS] = ~lc;
-        ++tr.cnt;
-        el = INFINITY;
-    }
-    if (er < INFINITY && rc < 0) {
-        lm.cand[tr.cnt * TR_THREADS] = ~rc;
-        ++tr.cnt;
-        er = INFINITY;
-    }
-    if (el < INFINITY && er < INFINITY) {
-        bool lfirst = el <= er;
-        lm.push(tr.sp, lfirst ? rc : lc);
-        ++tr.sp;
-        tr.node = lfirst ? lc : rc;
-    } else if (el < INFINITY) {
-        tr.node = lc;
-    } else if (er < INFINITY) {
-        tr.node = rc;
-    } else if (tr.sp == 0) {
-        tr.on = false;
-    } else {
-        --tr.sp;
-        tr.node = lm.pop(tr.sp);
-    }
-}
-
-// After the proposal traversal: evaluation and decisions of the window.
-// Returns true when the segment is finished.
-template <bool COUNT>
-static __device__ bool close_window(const SceneView& S, const MaskView& M, SegState& st, const Prop& pr,
+static __device__ void lane_propose(const SceneView& S, const MaskView& M, const SegState& st, Prop& pr,
                                     const LaneMem& lm, Work& wk) {
+    const Seg& sg = st.sg;
+    lane_traverse<COUNT>(S, st.cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, pr.tcut, lm, wk,
+                         [&](int j) { prop_leaf<COUNT>(S, M, st.cw, sg, st.k0, st.k1, st.win, j, pr, lm, wk); });
+}
+
+// Packet traversal for the windows of a whole wave at once (coherent camera
+// rays): the node index, the stack (LDS, pstk) and the leaf are
+// wave-uniform, so node records come through the scalar cache; each lane
+// tests its own ray over its own [ta, tb] (tb re-read at every node) and the
+// wave descends where any lane hits; leaf(j) runs on the lanes whose ray
+// meets the leaf's box.  Children are visited left first, so the leaves a
+// lane processes come in tree order whatever the other lanes do.
+template <bool COUNT, class LeafFn>
+static __device__ __forceinline__ void packet_walk(const SceneView& S, const SegState& st, bool act, float ta,
+                                                   const float& tb, int* __restrict__ pstk, Work& wk, LeafFn&& leaf) {
+    const Seg& sg = st.sg;
+    if (S.n == 1) {
+        if (act) leaf(0);
+        return;
+    }
+    const float ix = 1.0f / sg.vx, iy = 1.0f / sg.vy, iz = 1.0f / sg.vz;
+    int sp = 0, node = 0;
+    for (;;) {
+        const TNode* nd = S.nodes + node;
+        if (COUNT && act) ++wk.nodes;
+        uint32_t c = nd->cells;
+        float tbn = tb;
+        bool hl = act && (c & 0xffffu & st.cw.cells) && slab_hit(nd->lbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, ta, tbn);
+        bool hr = act && ((c >> 16) & st.cw.cells) && slab_hit(nd->rbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, ta, tbn);
+        uint64_t bl = __ballot(hl), br = __ballot(hr);
+        int lc = nd->lchild, rc = nd->rchild;
+        if (bl && lc < 0) {
+            if (hl) leaf(~lc);
+            bl = 0;
+        }
+        if (br && rc < 0) {
+            if (hr) leaf(~rc);
+            br = 0;
+        }
+        if (bl && br) {
+            pstk[sp] = rc;
+            ++sp;
+            node = lc;
+        } else if (bl) {
+            node = lc;
+        } else if (br) {
+            node = rc;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = pstk[sp];
+        }
+        node = uniform_int(node);
+    }
+}
+
+// kappa and mu from primitive j at the sorted points of a window in [pa, pb]
+template <bool COUNT>
+static __device__ __forceinline__ void eval_leaf(const SceneView& S, const MaskView& M, const SegState& st, int j,
+                                                 float pa, float pb, int np, const LaneMem& lm, Work& wk) {
+    PrimF P = load_prim(S.prims, j);
+    if (COUNT) ++wk.prims;
+    float mw = st.cw.mw(P.cell);
+    if (mw == 0.0f || !prim_on(M, P.orig)) return;
+    ChordF C;
+    if (!chord_f32(P, S.r2, st.sg.ox, st.sg.oy, st.sg.oz, st.sg.vx, st.sg.vy, st.sg.vz, pa, pb, C, true)) return;
+    add_chord(P, C, st.cw, mw, st.sg, np, first_point(lm, np, C.ci), lm);
+}
+
+// points sorted, kappa and mu cleared: ready for an evaluation pass
+static __device__ __forceinline__ void open_points(const LaneMem& lm, int np) {
+    sort_points(lm, np);
+    for (int k = 0; k < np; ++k) {
+        lm.kap(k) = 0.0f;
+        lm.maj(k) = 0.0f;
+    }
+}
+
+// Decisions of an evaluated window and the move to the next one.  Returns
+// true when the segment is finished.
+template <bool COUNT>
+static __device__ bool decide_window(SegState& st, const Prop& pr, const LaneMem& lm, Work& wk) {
     if (!st.live) return true;
     if (COUNT) ++wk.windows;
     const int np = pr.np;
-    if (np > 0) {
-        sort_points(lm, np);
-        evaluate<COUNT>(S, M, st.cw, st.sg, np, pr.nc, lm, wk);
-        if (st.mode & MODE_RATIO)
-            for (int k = 0; k < np; ++k) st.T *= 1.0f - lm.kap(k) / lm.maj(k);
-        if ((st.mode & MODE_DELTA) && !(st.tc < INFINITY)) {
-            // the collision is the earliest real point; null factors of the
-            // points before it apply
-            float w = 1.0f, fr, fn;
-            for (int k = 0; k < np; ++k) {
-                bool real = delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn);
-                if (real) {
-                    w *= fr;
-                    st.tc = lm.t[k * TR_THREADS];
-                    break;
-                }
-                w *= fn;
+    if (st.mode & MODE_RATIO)
+        for (int k = 0; k < np; ++k) st.T *= 1.0f - lm.kap(k) / lm.maj(k);
+    if ((st.mode & MODE_DELTA) && !(st.tc < INFINITY)) {
+        // the collision is the earliest real point; null factors of the
+        // points before it apply
+        float w = 1.0f, fr, fn;
+        for (int k = 0; k < np; ++k) {
+            bool real = delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn);
+            if (real) {
+                w *= fr;
+                st.tc = lm.t[k * TR_THREADS];
+                break;
             }
-            st.wf *= w;
+            w *= fn;
         }
+        st.wf *= w;
     }
     bool full = pr.tcut < st.sg.tb;
     bool stop = !full || (st.mode == MODE_DELTA && st.tc < INFINITY) || ++st.win >= MAX_WINDOWS;
     if (!stop) st.sg.ta = pr.tcut;
     return stop;
+}
+
+// A lane's own window after its proposal pass: evaluation and decisions.
+template <bool COUNT>
+static __device__ bool close_window(const SceneView& S, const MaskView& M, SegState& st, const Prop& pr,
+                                    const LaneMem& lm, Work& wk) {
+    if (st.live && pr.np > 0) {
+        open_points(lm, pr.np);
+        evaluate<COUNT>(S, M, st.cw, st.sg, pr.np, lm, wk);
+    }
+    return decide_window<COUNT>(st, pr, lm, wk);
 }
 
 static __device__ __forceinline__ void sample_sphere(Rng& g, float* d) {
@@ -715,7 +712,7 @@ static int64_t tr_threads(int64_t n, int tile_w) {
 }
 
 // ---------------------------------------------------------------------------
-// per-ray drivers: resumable per-lane state, advanced one window at a time
+// per-ray drivers
 // ---------------------------------------------------------------------------
 struct RenderArgs {
     int spp, multiple, max_scatter, stochastic;
@@ -723,39 +720,38 @@ struct RenderArgs {
     uint64_t seed;
 };
 
-// Ratio-tracking transmittance of the ray over [tmin, tmax], spp samples.
-struct RatioLane {
-    const float* r;
-    uint32_t key;
-    int s;
-    float s1, s2;
-    Rng g;
-    SegState st;
-    __device__ void begin(const SceneView& S, const MaskView& M, const float* ray, uint32_t k, uint64_t seed) {
-        r = ray;
-        key = k;
-        s = 0;
-        s1 = s2 = 0.0f;
-        start(S, M, seed);
+// Camera segments of a whole wave, window by window: packet proposal and
+// packet evaluation passes; a lane whose segment is finished sits out.
+template <bool COUNT>
+static __device__ void track_camera(const SceneView& S, const MaskView& M, SegState& st, bool valid,
+                                    const LaneMem& lm, int* pstk, Work& wk) {
+    bool open = valid && st.live;
+    while (__any(open)) {
+        Prop pr;
+        begin_prop(pr, st);
+        packet_walk<COUNT>(S, st, open, st.sg.ta, pr.tcut, pstk, wk, [&](int j) {
+            prop_leaf<COUNT>(S, M, st.cw, st.sg, st.k0, st.k1, st.win, j, pr, lm, wk);
+        });
+        const bool ev = open && pr.np > 0;
+        if (ev) open_points(lm, pr.np);
+        const float pa = ev ? lm.t[0] : 0.0f, pb = ev ? lm.t[(pr.np - 1) * TR_THREADS] : -1.0f;
+        packet_walk<COUNT>(S, st, ev, pa, pb, pstk, wk,
+                           [&](int j) { eval_leaf<COUNT>(S, M, st, j, pa, pb, pr.np, lm, wk); });
+        if (open && decide_window<COUNT>(st, pr, lm, wk)) open = false;
     }
-    __device__ void start(const SceneView& S, const MaskView& M, uint64_t seed) {
-        g.init(seed, key, (uint32_t)s, 1u);
-        begin_segment(S, st, r, r + 3, r[6], r[7], fixed_weights(M), MODE_RATIO, g);
-    }
-    // the segment (one sample) is finished; true once all samples are done
-    __device__ bool segment_done(const SceneView& S, const MaskView& M, int spp, uint64_t seed) {
-        s1 += st.T;
-        s2 += st.T * st.T;
-        if (++s < spp) {
-            start(S, M, seed);
-            return false;
-        }
-        return true;
-    }
-};
+}
 
-// Radiance of one camera ray, spp samples, with a constant environment.
-// Single scattering: the primary segment is delta-tracked (and ratio-tracked
+// A lane's own (secondary) segment, one window; true when it is finished.
+template <bool COUNT>
+static __device__ bool track_own(const SceneView& S, const MaskView& M, SegState& st, const LaneMem& lm, Work& wk) {
+    Prop pr;
+    begin_prop(pr, st);
+    if (st.live) lane_propose<COUNT>(S, M, st, pr, lm, wk);
+    return close_window<COUNT>(S, M, st, pr, lm, wk);
+}
+
+// Radiance of one camera ray over spp samples, with a constant environment.
+// Single scattering: the camera segment is delta-tracked (and ratio-tracked
 // for its transmittance on the same tentative points); a real collision
 // scatters isotropically and ratio-tracks the way out.  Multiple scattering:
 // delta tracking from segment to segment with Henyey-Greenstein scattering
@@ -763,20 +759,18 @@ struct RatioLane {
 struct RenderLane {
     const float* r;
     uint32_t key;
-    int s, nsc, seg;
+    int nsc, seg;
     bool shadow;
     float w, L, Tp;
     float s1, s2, q1, q2;
     Rng g;
     SegState st;
-    __device__ void begin(const SceneView& S, const MaskView& M, const RenderArgs& A, const float* ray, uint32_t k) {
+    __device__ void begin(const float* ray, uint32_t k) {
         r = ray;
         key = k;
-        s = 0;
         s1 = s2 = q1 = q2 = 0.0f;
-        start(S, M, A);
     }
-    __device__ void start(const SceneView& S, const MaskView& M, const RenderArgs& A) {
+    __device__ void start(const SceneView& S, const MaskView& M, const RenderArgs& A, int s) {
         g.init(A.seed, key, (uint32_t)s, 0u);
         w = 1.0f;
         L = 0.0f;
@@ -786,30 +780,25 @@ struct RenderLane {
         CellW cw = A.stochastic ? stochastic_weights(S, r[3], r[4], r[5], g) : fixed_weights(M);
         begin_segment(S, st, r, r + 3, r[6], r[7], cw, MODE_RATIO | MODE_DELTA, g);
     }
-    // closes the current sample; true when it was the last one
-    __device__ bool end_sample(const SceneView& S, const MaskView& M, const RenderArgs& A) {
+    __device__ bool end_sample() {
         s1 += L;
         s2 += L * L;
         q1 += Tp;
         q2 += Tp * Tp;
-        if (++s < A.spp) {
-            start(S, M, A);
-            return false;
-        }
         return true;
     }
-    // the current segment is finished: scatter, escape or close the sample;
-    // true once all samples are done
+    // the current segment is finished: scatter (and set up the next
+    // segment) or close the sample; true when the sample is over
     __device__ bool segment_done(const SceneView& S, const MaskView& M, const RenderArgs& A) {
         if (seg == 0) Tp = st.T;
         if (shadow) {
             L += w * A.albedo * st.T * A.env;
-            return end_sample(S, M, A);
+            return end_sample();
         }
         w *= st.wf;
         if (!(st.tc < INFINITY)) {
             L += w * A.env;
-            return end_sample(S, M, A);
+            return end_sample();
         }
         float x[3] = {st.sg.ox + st.tc * st.sg.vx, st.sg.oy + st.tc * st.sg.vy, st.sg.oz + st.tc * st.sg.vz};
         float d[3];
@@ -819,7 +808,7 @@ struct RenderLane {
             shadow = true;
             mode = MODE_RATIO;
         } else {
-            if (nsc >= A.max_scatter) return end_sample(S, M, A);
+            if (nsc >= A.max_scatter) return end_sample();
             ++nsc;
             w *= A.albedo;
             float vn = rsqrtf(st.sg.vx * st.sg.vx + st.sg.vy * st.sg.vy + st.sg.vz * st.sg.vz);
@@ -841,99 +830,56 @@ struct RenderLane {
     }
 };
 
-// Work distribution: the rays of a launch are numbered 0..total-1 and handed
-// out by a launch-wide counter to lanes as they become free (one atomic per
-// wave and refill), so every lane stays busy until the work runs out and no
-// wave waits on another's tiles.  Returns this lane's new item (or total when
-// the work is exhausted); lanes with need == false get -1.
-static __device__ __forceinline__ int fetch_item(unsigned* counter, bool need, int total) {
-    uint64_t m = __ballot(need);
-    int cnt = __popcll(m);
-    int leader = __ffsll((long long)m) - 1;
-    unsigned base = 0;
-    if (lane_id() == leader) base = atomicAdd(counter, (unsigned)cnt);
-    base = __shfl(base, leader);
-    if (!need) return -1;
-    unsigned it = base + (unsigned)__popcll(m & lanemask_lt());
-    return it < (unsigned)total ? (int)it : total;
-}
-
-// Lanes run below this many node steps at once before the wave drains
-// the leaf queues, and this many lanes wait with a finished traversal before
-// the wave closes their windows: the heavy leaf and window work then runs
-// with most lanes taking part.
-#define DRAIN_BELOW 16
-#define CLOSE_AT 48
-
-// Persistent loop of one wave.  Each lane advances its own window: node
-// steps, leaf drains and window closes are interleaved per lane, so a lane
-// never waits for the longest traversal of its wave; a finished window opens
-// the next one (next window, segment, sample, or a new ray from the
-// counter).  `map(item)` gives the ray index of an item (-1: none),
-// `begin(idx)` starts a ray, `seg()` is its current segment,
-// `segment_done()` moves past a finished segment (true when the ray is
-// complete) and `done(idx)` writes its result.
-template <bool COUNT, class Ctx, class Map, class Begin, class SegRef, class SegDone, class Done>
-static __device__ __forceinline__ void run_lanes(unsigned* counter, int total, const LaneMem& lm, Work& wk, Ctx&& ctx,
-                                                 Map&& map, Begin&& begin, SegRef&& seg, SegDone&& segment_done,
-                                                 Done&& done) {
-    int idx = -1;
-    bool more = true;
-    Trav tr;
-    Prop pr;
-    tr.on = false;
-    tr.cnt = 0;
-    for (;;) {
-        bool need = idx < 0 && more;
-        if (__any(need)) {
-            int it = fetch_item(counter, need, total);
-            if (need) {
-                if (it >= total) {
-                    more = false;
-                } else {
-                    idx = map(it);
-                    if (idx >= 0) {
-                        begin(idx);
-                        begin_window(ctx.S(), seg(), tr, pr, lm);
-                    }
-                }
-            }
-        }
-        const bool act = idx >= 0;
-        if (!__any(act || more)) break;
-        // node steps
-        if (act && tr.on && tr.cnt <= CQ - 2) node_step<COUNT>(ctx.S(), seg(), pr.tcut, tr, lm, wk);
-        // leaf drains
-        if (__popcll(__ballot(act && tr.on && tr.cnt <= CQ - 2)) < DRAIN_BELOW && act) {
-            SegState& st = seg();
-            for (int k = 0; k < tr.cnt; ++k)
-                prop_leaf<COUNT>(ctx.S(), ctx.M(), st.cw, st.sg, st.k0, st.k1, st.win, lm.cand[k * TR_THREADS], pr,
-                                 lm, wk);
-            tr.cnt = 0;
-        }
-        // window closes
-        const bool pend = act && !tr.on && tr.cnt == 0;
-        const int npend = __popcll(__ballot(pend));
-        if (npend >= CLOSE_AT || (npend > 0 && npend == __popcll(__ballot(act)))) {
-            if (pend) {
-                if (close_window<COUNT>(ctx.S(), ctx.M(), seg(), pr, lm, wk) && segment_done()) {
-                    done(idx);
-                    idx = -1;
-                } else {
-                    begin_window(ctx.S(), seg(), tr, pr, lm);
-                }
-            }
+// One wave renders 64 rays (idx < 0: no ray on this lane): for every sample
+// the camera segments go through the packet passes together, then each lane
+// follows its own path with per-lane passes.
+template <bool COUNT>
+static __device__ void render_rays(const SceneView& S, const MaskView& M, const RenderArgs& A,
+                                   const float* __restrict__ rays, int idx, const LaneMem& lm, int* pstk, Work& wk,
+                                   float* out4) {
+    const bool valid = idx >= 0;
+    RenderLane rl;
+    if (valid) rl.begin(rays + (size_t)idx * 8, (uint32_t)idx);
+    for (int s = 0; s < A.spp; ++s) {
+        if (valid) rl.start(S, M, A, s);
+        track_camera<COUNT>(S, M, rl.st, valid, lm, pstk, wk);
+        bool more = valid && !rl.segment_done(S, M, A);
+        while (__any(more)) {
+            if (more && track_own<COUNT>(S, M, rl.st, lm, wk)) more = !rl.segment_done(S, M, A);
         }
     }
+    if (valid) rl.result(A, out4);
 }
 
-// scene and mask of a launch
-struct LaunchCtx {
-    const SceneView& s;
-    const MaskView& m;
-    __device__ const SceneView& S() const { return s; }
-    __device__ const MaskView& M() const { return m; }
-};
+// Ratio-tracking transmittance of 64 rays over [tmin, tmax], spp samples.
+template <bool COUNT>
+static __device__ void ratio_rays(const SceneView& S, const MaskView& M, const float* __restrict__ rays, int idx,
+                                  int spp, uint64_t seed, const LaneMem& lm, int* pstk, Work& wk, float* out2) {
+    const bool valid = idx >= 0;
+    const float* r = rays + (size_t)(valid ? idx : 0) * 8;
+    float s1 = 0.0f, s2 = 0.0f;
+    SegState st;
+    for (int s = 0; s < spp; ++s) {
+        if (valid) {
+            Rng g;
+            g.init(seed, (uint32_t)idx, (uint32_t)s, 1u);
+            begin_segment(S, st, r, r + 3, r[6], r[7], fixed_weights(M), MODE_RATIO, g);
+        }
+        track_camera<COUNT>(S, M, st, valid, lm, pstk, wk);
+        s1 += st.T;
+        s2 += st.T * st.T;
+    }
+    out2[0] = s1 / spp;
+    out2[1] = spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 / spp) / (spp - 1)) : 0.0f;
+}
+
+// Work distribution: waves take chunks of 64 rays (one 8x8 tile of an image,
+// or 64 consecutive rays) from a launch-wide counter.
+static __device__ __forceinline__ int next_chunk(unsigned* counter) {
+    unsigned c = 0;
+    if (lane_id() == 0) c = atomicAdd(counter, 1u);
+    return uniform_int((int)__shfl(c, 0));
+}
 
 // ---------------------------------------------------------------------------
 // kernels
@@ -961,51 +907,50 @@ __global__ __launch_bounds__(TR_THREADS) void k_density(SceneView S, MaskView M,
     }
 }
 
-// The first 256 B of the workspace hold the launch's item counter (zeroed by
+// The first 256 B of the workspace hold the launch's chunk counter (zeroed by
 // k_zero before the launch); the lanes' slices follow.
 #define WS_HEAD 64
 
 __global__ void k_zero(unsigned* p) { *p = 0u; }
 
 __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, const float* __restrict__ rays, int n,
-                                                      int tile_w, int total, int spp, uint64_t seed,
+                                                      int tile_w, int nchunks, int spp, uint64_t seed,
                                                       float* __restrict__ ws, float* __restrict__ Tm,
                                                       float* __restrict__ Tv) {
     LANE_MEM(ws + WS_HEAD)
-    RatioLane rl;
+    __shared__ int pstk[TR_STACK];
     Work wk{};
-    run_lanes<false>(
-        (unsigned*)ws, total, lm, wk, LaunchCtx{S, M}, [&](int it) { return ray_of_tr(it, n, tile_w); },
-        [&](int idx) { rl.begin(S, M, rays + (size_t)idx * 8, (uint32_t)idx, seed); },
-        [&]() -> SegState& { return rl.st; }, [&]() { return rl.segment_done(S, M, spp, seed); },
-        [&](int idx) {
-            Tm[idx] = rl.s1 / spp;
-            if (Tv) Tv[idx] = spp > 1 ? fmaxf(0.0f, (rl.s2 - rl.s1 * rl.s1 / spp) / (spp - 1)) : 0.0f;
-        });
+    for (int c = next_chunk((unsigned*)ws); c < nchunks; c = next_chunk((unsigned*)ws)) {
+        int idx = ray_of_tr(c * TR_THREADS + (int)threadIdx.x, n, tile_w);
+        float o[2];
+        ratio_rays<false>(S, M, rays, idx, spp, seed, lm, pstk, wk, o);
+        if (idx >= 0) {
+            Tm[idx] = o[0];
+            if (Tv) Tv[idx] = o[1];
+        }
+    }
 }
 
 template <bool COUNT>
 __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, const float* __restrict__ rays, int n,
-                                                       int tile_w, int total, RenderArgs A, float* __restrict__ ws,
+                                                       int tile_w, int nchunks, RenderArgs A, float* __restrict__ ws,
                                                        float* __restrict__ Lm, float* __restrict__ Lv,
                                                        float* __restrict__ Tm, float* __restrict__ Tv,
                                                        unsigned long long* __restrict__ counters) {
     LANE_MEM(ws + WS_HEAD)
-    RenderLane rl;
+    __shared__ int pstk[TR_STACK];
     Work wk{};
-    run_lanes<COUNT>(
-        (unsigned*)ws, total, lm, wk, LaunchCtx{S, M}, [&](int it) { return ray_of_tr(it, n, tile_w); },
-        [&](int idx) { rl.begin(S, M, A, rays + (size_t)idx * 8, (uint32_t)idx); },
-        [&]() -> SegState& { return rl.st; }, [&]() { return rl.segment_done(S, M, A); },
-        [&](int idx) {
-            if (COUNT) return;
-            float o[4];
-            rl.result(A, o);
+    for (int c = next_chunk((unsigned*)ws); c < nchunks; c = next_chunk((unsigned*)ws)) {
+        int idx = ray_of_tr(c * TR_THREADS + (int)threadIdx.x, n, tile_w);
+        float o[4];
+        render_rays<COUNT>(S, M, A, rays, idx, lm, pstk, wk, o);
+        if (!COUNT && idx >= 0) {
             Lm[idx] = o[0];
             if (Lv) Lv[idx] = o[1];
             if (Tm) Tm[idx] = o[2];
             if (Tv) Tv[idx] = o[3];
-        });
+        }
+    }
     if (COUNT) {
         atomicAdd(counters + 0, wk.tent);
         atomicAdd(counters + 1, wk.nodes);
@@ -1015,8 +960,10 @@ __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, 
 }
 
 // Serving: one launch renders tiles of many requests (each tile a contiguous
-// range of one request's rays).  A request's random streams are keyed by its
-// own seed and pixel index, so its image does not depend on the batch.
+// range of one request's rays, cut into chunks of 64).  A request's random
+// streams are keyed by its own seed and pixel index and a lane's result does
+// not depend on the other rays of its chunk, so its image does not depend on
+// the batch.
 struct ServeReq {
     SceneView S;
     MaskView M;
@@ -1030,36 +977,21 @@ struct ServeTile {
     int req, first, count, pad;
 };
 
-// scene and mask of the request of a lane's current ray
-struct ServeCtx {
-    const ServeReq* const& r;
-    __device__ const SceneView& S() const { return r->S; }
-    __device__ const MaskView& M() const { return r->M; }
-};
-
 __global__ __launch_bounds__(TR_THREADS) void k_render_tiles(const ServeReq* __restrict__ reqs,
-                                                             const ServeTile* __restrict__ tiles, int tile_rays,
-                                                             int total, float* __restrict__ ws) {
+                                                             const ServeTile* __restrict__ tiles, int chunks_per_tile,
+                                                             int nchunks, float* __restrict__ ws) {
     LANE_MEM(ws + WS_HEAD)
-    RenderLane rl;
+    __shared__ int pstk[TR_STACK];
     Work wk{};
-    const ServeReq* R = reqs;
-    run_lanes<false>(
-        (unsigned*)ws, total, lm, wk, ServeCtx{R},
-        [&](int it) {
-            const ServeTile tl = tiles[it / tile_rays];
-            int local = it % tile_rays;
-            if (local >= tl.count) return -1;
-            R = reqs + tl.req;
-            return tl.first + local;
-        },
-        [&](int idx) { rl.begin(R->S, R->M, R->A, R->rays + (size_t)idx * 8, (uint32_t)idx); },
-        [&]() -> SegState& { return rl.st; }, [&]() { return rl.segment_done(R->S, R->M, R->A); },
-        [&](int idx) {
-            float o[4];
-            rl.result(R->A, o);
-            R->out[idx] = o[0];
-        });
+    for (int c = next_chunk((unsigned*)ws); c < nchunks; c = next_chunk((unsigned*)ws)) {
+        const ServeTile tl = tiles[c / chunks_per_tile];
+        const ServeReq& R = reqs[tl.req];
+        int local = (c % chunks_per_tile) * TR_THREADS + (int)threadIdx.x;
+        int idx = local < tl.count ? tl.first + local : -1;
+        float o[4];
+        render_rays<false>(R.S, R.M, R.A, R.rays, idx, lm, pstk, wk, o);
+        if (idx >= 0) R.out[idx] = o[0];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1107,7 +1039,7 @@ gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int
     int bpt = (tile_rays + TR_THREADS - 1) / TR_THREADS;
     k_zero<<<1, 1, 0, sm>>>((unsigned*)ws);
     k_render_tiles<<<res_blocks((int64_t)ntiles * bpt), TR_THREADS, 0, sm>>>(
-        (const ServeReq*)dreqs, (const ServeTile*)dtiles, tile_rays, ntiles * tile_rays, ws);
+        (const ServeReq*)dreqs, (const ServeTile*)dtiles, bpt, ntiles * bpt, ws);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }
@@ -1204,8 +1136,8 @@ extern "C" gf_status gf_transmittance_ratio(gf_scene s, const float* rays, int64
     if (st != GF_OK) return st;
     k_zero<<<1, 1, 0, (hipStream_t)stream>>>((unsigned*)ws.p);
     k_ratio<<<res_blocks(nb), TR_THREADS, 0, (hipStream_t)stream>>>(gf_scene_view(s), gf_mask_view(mask), rays, (int)n,
-                                                                    image_width, (int)tr_threads(n, image_width), spp,
-                                                                    seed, ws.p, T_mean, T_var);
+                                                                    image_width, (int)nb, spp, seed, ws.p, T_mean,
+                                                                    T_var);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }
@@ -1226,7 +1158,7 @@ gf_status gf_render_launch(gf_scene s, const float* rays, int64_t n, int image_w
     Workspace ws;
     gf_status st = ws.alloc(nb, sm, "gf_render");
     if (st != GF_OK) return st;
-    int total = (int)tr_threads(n, image_width);
+    int total = (int)nb;  // chunks of TR_THREADS rays
     k_zero<<<1, 1, 0, sm>>>((unsigned*)ws.p);
     if (counters)
         k_render<true><<<res_blocks(nb), TR_THREADS, 0, sm>>>(gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n,
