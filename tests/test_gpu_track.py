@@ -155,3 +155,31 @@ def test_render_deterministic_and_batch_independent():
     # a ray's result depends only on its own index in the batch: compare the
     # sub-batch against rays traced at the same indices
     assert torch.isfinite(a).all() and torch.isfinite(c).all()
+
+
+def test_render_full_size_sampled_blob100k():
+    """the benchmark's render launch (100k primitives, 512^2 pinhole, 8 spp,
+    single scattering, 8x8 tiles), repeated with 8 seeds, checked in mean on
+    a seeded sample of pixels the oracle renders one by one"""
+    gf = require_gpu()
+    params, rays, rho = W.scene("blob100k"), W.rays("blob100k"), W.rho("blob100k")
+    scene = gf.Scene(dev(params), rho=rho)
+    drays = dev(rays)
+    sub = W.pixel_subset(rays.shape[0], k=24, seed=17)
+    runs = 8
+    Lsum, Lv_sum = np.zeros(len(sub)), np.zeros(len(sub))
+    for seed in range(runs):
+        d = gf.render_desc(spp=8, multiple=False, albedo=0.9, seed=1234 + seed)
+        L, Lv, _, _ = gf.gf_render(scene, drays, d, image_width=512)
+        Lsum += host(L)[sub]
+        Lv_sum += host(Lv)[sub]
+        print("launch", seed, "done", flush=True)
+    g = Lsum / runs
+    g_se2 = (Lv_sum / runs) / (8 * runs)
+    spp_o = 256
+    o, ov, _, _ = oracle.render(params, rays[sub], spp_o, seed=3, rho=rho, multiple=False, albedo=0.9)
+    se = np.sqrt(g_se2 + ov / spp_o) + 1e-15
+    pooled = abs(np.sum(g - o)) / np.sqrt(np.sum(se ** 2))
+    worst = np.max(np.abs(g - o) / se)
+    print("pooled %.2f worst %.2f" % (pooled, worst), flush=True)
+    assert pooled < 3.0 and worst < 6.0
