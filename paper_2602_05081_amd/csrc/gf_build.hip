@@ -293,7 +293,8 @@ static __device__ __forceinline__ int kdelta(const uint64_t* __restrict__ k, int
 }
 
 __global__ __launch_bounds__(256) void k_karras(const uint64_t* __restrict__ keys, int n, int32_t* __restrict__ left,
-                                                int32_t* __restrict__ right, int32_t* __restrict__ parent) {
+                                                int32_t* __restrict__ right, int32_t* __restrict__ parent,
+                                                int2* __restrict__ range) {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n - 1) return;
     int d = (kdelta(keys, n, i, i + 1) - kdelta(keys, n, i, i - 1)) > 0 ? 1 : -1;
@@ -319,6 +320,7 @@ __global__ __launch_bounds__(256) void k_karras(const uint64_t* __restrict__ key
     right[i] = rc;
     parent[lc] = i;
     parent[rc] = i;
+    range[i] = make_int2(first, last);
 }
 
 // ---------------------------------------------------------------------------
@@ -438,6 +440,31 @@ __global__ __launch_bounds__(256) void k_tnodes(int n, const int32_t* __restrict
     nodes[i] = t;
 }
 
+// Traversal records with every subtree of at most GF_LEAF_MAX primitives
+// collapsed into a Morton leaf range (fewer dependent node steps for the
+// per-lane traversals; the subtree's box and cell mask stay those of its
+// root).
+__global__ __launch_bounds__(256) void k_tnodes_collapsed(int n, const int32_t* __restrict__ left,
+                                                          const int32_t* __restrict__ right,
+                                                          const int2* __restrict__ range,
+                                                          const TNode* __restrict__ nodes,
+                                                          TNode* __restrict__ cnodes) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n - 1) return;
+    const int L0 = n - 1;
+    auto enc = [&](int a) -> int {
+        if (a >= L0) return ~(a - L0);
+        int2 r = range[a];
+        int cnt = r.y - r.x + 1;
+        if (cnt <= GF_LEAF_MAX) return ~(int)((unsigned)r.x | ((unsigned)(cnt - 1) << 28));
+        return a;
+    };
+    TNode t = nodes[i];
+    t.lchild = enc(left[i]);
+    t.rchild = enc(right[i]);
+    cnodes[i] = t;
+}
+
 // ---------------------------------------------------------------------------
 // 8. majorant grid: per voxel and cell, sum over primitives whose leaf box
 //    meets the voxel of rho |alpha| c exp(-m / 2), with m a lower bound of the
@@ -522,7 +549,8 @@ __global__ __launch_bounds__(256) void k_cells_export(const float4* __restrict__
 // ---------------------------------------------------------------------------
 static gf_status scene_free(gf_scene_s* s) {
     if (!s) return GF_OK;
-    void* ptrs[] = {s->prims, s->aux, s->A64, s->nodes, s->grid, s->keys, s->perm, s->left, s->right, s->parent, s->aabb, s->cellor};
+    void* ptrs[] = {s->prims,  s->aux,  s->A64,   s->nodes,  s->cnodes, s->grid, s->keys,
+                    s->perm,   s->left, s->right, s->parent, s->aabb,   s->cellor};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete s;
@@ -580,6 +608,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     GF_TRY(dalloc(&s->aux, (size_t)n * 3, &total));
     GF_TRY(dalloc(&s->A64, (size_t)n * 6, &total));
     GF_TRY(dalloc(&s->nodes, (size_t)std::max<int64_t>(n - 1, 1), &total));
+    GF_TRY(dalloc(&s->cnodes, (size_t)std::max<int64_t>(n - 1, 1), &total));
     GF_TRY(dalloc(&s->grid, (size_t)G * G * G * GF_NCELLS, &total));
     GF_TRY(dalloc(&s->keys, (size_t)n, &total));
     GF_TRY(dalloc(&s->perm, (size_t)n, &total));
@@ -599,9 +628,10 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     int* visits = nullptr;
     float* kw = nullptr;
     unsigned long long* gacc = nullptr;
+    int2* ranges = nullptr;
     const int ntiles = (int)((n + RS_TILE - 1) / RS_TILE);
     auto cleanup = [&]() {
-        void* q[] = {parts, k2, v1, v2, hist, visits, kw, gacc};
+        void* q[] = {parts, k2, v1, v2, hist, visits, kw, gacc, ranges};
         for (void* x : q)
             if (x) (void)hipFree(x);
     };
@@ -622,6 +652,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     GF_STRY(dalloc(&visits, std::max<int64_t>(n - 1, 1), &scratch_bytes));
     GF_STRY(dalloc(&kw, n, &scratch_bytes));
     GF_STRY(dalloc(&gacc, (size_t)G * G * G * GF_NCELLS, &scratch_bytes));
+    GF_STRY(dalloc(&ranges, std::max<int64_t>(n - 1, 1), &scratch_bytes));
 
     // 1. validation, bounds, |f| max
     k_bounds_partial<<<nparts, 256, 0, sm>>>(params, ni, parts);
@@ -657,7 +688,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     // 4. hierarchy
     GF_STRY(hipMemsetAsync(s->parent, 0xff, sizeof(int32_t) * (2 * n - 1), sm) == hipSuccess
                 ? GF_OK : gf_hip_check(hipGetLastError(), "memset"));
-    if (n > 1) k_karras<<<nblk(n - 1), 256, 0, sm>>>(s->keys, ni, s->left, s->right, s->parent);
+    if (n > 1) k_karras<<<nblk(n - 1), 256, 0, sm>>>(s->keys, ni, s->left, s->right, s->parent, ranges);
     // 5. records and leaves
     k_leaves<<<nblk(n), 256, 0, sm>>>(params, ni, r, s->rho, parts, (const uint32_t*)s->perm, s->prims, s->aabb,
                                       s->cellor, kw, s->aux, s->A64);
@@ -667,6 +698,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
                     ? GF_OK : gf_hip_check(hipGetLastError(), "memset"));
         k_refit<<<nblk(n), 256, 0, sm>>>(ni, s->left, s->right, s->parent, s->aabb, s->cellor, visits);
         k_tnodes<<<nblk(n - 1), 256, 0, sm>>>(ni, s->left, s->right, s->aabb, s->cellor, s->nodes);
+        k_tnodes_collapsed<<<nblk(n - 1), 256, 0, sm>>>(ni, s->left, s->right, ranges, s->nodes, s->cnodes);
         GF_STRY(hipMemsetAsync(visits, 0, sizeof(int), sm) == hipSuccess
                     ? GF_OK : gf_hip_check(hipGetLastError(), "memset"));
         k_depth<<<nblk(n), 256, 0, sm>>>(ni, s->parent, visits);
@@ -822,6 +854,8 @@ SceneView gf_scene_view(const gf_scene_s* s) {
     SceneView v;
     v.prims = s->prims;
     v.nodes = s->nodes;
+    v.cnodes = s->cnodes;
+    v.croot = s->n <= GF_LEAF_MAX ? ~(int)((unsigned)(s->n - 1) << 28) : 0;
     v.grid = s->grid;
     v.aux = s->aux;
     v.A64 = s->A64;

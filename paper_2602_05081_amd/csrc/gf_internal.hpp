@@ -10,6 +10,10 @@
 //            holding both child boxes so one scalar load tests both children:
 //            [lbox lo/hi] [rbox lo/hi] [lchild rchild cells pad]; a child id
 //            c >= 0 is an internal node, c < 0 is the leaf (Morton index) ~c.
+//   cnodes : the same records with every subtree of at most GF_LEAF_MAX
+//            primitives collapsed into a leaf range: c < 0 is the Morton
+//            range first = ~c & 0x0FFFFFFF, count = (~c >> 28) + 1 (the
+//            subtree's primitives are contiguous in Morton order).
 //   A64    : n x 48 B, Sigma^-1 in binary64 for the chord geometry of the
 //            optical-depth and adjoint kernels (float32 rounding of an
 //            anisotropic Sigma^-1 moves h^2 by ~1e-5 relative).
@@ -25,6 +29,14 @@
 
 #define GF_NCELLS 12
 #define GF_STACK 128
+#define GF_LEAF_MAX 4
+
+// Leaf range of a collapsed child id c < 0.
+static __device__ __forceinline__ void leaf_range(int c, int* first, int* count) {
+    unsigned v = ~(unsigned)c;
+    *first = (int)(v & 0x0FFFFFFFu);
+    *count = (int)(v >> 28) + 1;
+}
 
 struct TNode {
     float lbox[6];
@@ -39,6 +51,8 @@ static_assert(sizeof(TNode) == 64, "traversal node must be 64 bytes");
 struct SceneView {
     const float4* __restrict__ prims;
     const TNode* __restrict__ nodes;
+    const TNode* __restrict__ cnodes;  // the same tree with small subtrees collapsed into leaf ranges
+    int croot;                         // root as a leaf range (< 0) when the whole scene is one, else 0
     const float* __restrict__ grid;
     const float4* __restrict__ aux;
     const double* __restrict__ A64;  // Sigma^-1 in binary64, 6 per primitive (a00 a01 a02 a11 a12 a22)
@@ -71,6 +85,7 @@ struct gf_scene_s {
     float4* aux;  // adjoint data, 3 x float4 per primitive (Morton
                   // order): [q w x y z (caller's)] [|q| s0 s1 s2] [alpha, rho/(4 pi s0 s1 s2), 0, 0]
     TNode* nodes;
+    TNode* cnodes;
     float* grid;
     uint64_t* keys;
     int32_t* perm;

@@ -244,6 +244,19 @@ static __device__ __forceinline__ bool chord_f32(const PrimF& P, float r2, float
     return true;
 }
 
+// first point (ascending) at or after t
+static __device__ __forceinline__ int first_point(const LaneMem& lm, int np, float t) {
+    int lo = 0, hi = np;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (lm.t[mid * TR_THREADS] < t)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // entry distance of the ray into box b within [tmin, tmax] (INFINITY: miss);
 // the same conservative test as slab_hit
 static __device__ __forceinline__ float slab_enter(const float* b, float ox, float oy, float oz, float ix, float iy,
@@ -267,8 +280,13 @@ template <bool COUNT, class LeafFn>
 static __device__ __forceinline__ void lane_traverse(const SceneView& S, uint32_t cells, float ox, float oy, float oz,
                                                      float vx, float vy, float vz, float ta, const float& tb,
                                                      const LaneMem& lm, Work& wk, LeafFn&& leaf) {
-    if (S.n == 1) {
-        leaf(0);
+    auto leaves = [&](int c) {
+        int first, count;
+        leaf_range(c, &first, &count);
+        for (int k = 0; k < count; ++k) leaf(first + k);
+    };
+    if (S.croot < 0) {
+        leaves(S.croot);
         return;
     }
     const float ix = 1.0f / vx, iy = 1.0f / vy, iz = 1.0f / vz;
@@ -280,13 +298,13 @@ static __device__ __forceinline__ void lane_traverse(const SceneView& S, uint32_
     for (;;) {
         bool step = trav && cnt <= CQ - 2;
         if (!__any(step)) {
-            for (int k = 0; k < cnt; ++k) leaf(lm.cand[k * TR_THREADS]);
+            for (int k = 0; k < cnt; ++k) leaves(lm.cand[k * TR_THREADS]);
             cnt = 0;
             if (!__any(trav)) break;
             continue;
         }
         if (!step) continue;
-        const TNode* nd = S.nodes + node;
+        const TNode* nd = S.cnodes + node;
         if (COUNT) ++wk.nodes;
         uint32_t c = nd->cells;
         float tbn = tb;
@@ -294,12 +312,12 @@ static __device__ __forceinline__ void lane_traverse(const SceneView& S, uint32_
         float er = ((c >> 16) & cells) ? slab_enter(nd->rbox, ox, oy, oz, ix, iy, iz, ta, tbn) : INFINITY;
         int lc = nd->lchild, rc = nd->rchild;
         if (el < INFINITY && lc < 0) {
-            lm.cand[cnt * TR_THREADS] = ~lc;
+            lm.cand[cnt * TR_THREADS] = lc;
             ++cnt;
             el = INFINITY;
         }
         if (er < INFINITY && rc < 0) {
-            lm.cand[cnt * TR_THREADS] = ~rc;
+            lm.cand[cnt * TR_THREADS] = rc;
             ++cnt;
             er = INFINITY;
         }
@@ -449,18 +467,6 @@ static __device__ __forceinline__ void add_chord(const PrimF& P, const ChordF& C
     }
 }
 
-// first point (ascending) at or after t
-static __device__ __forceinline__ int first_point(const LaneMem& lm, int np, float t) {
-    int lo = 0, hi = np;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (lm.t[mid * TR_THREADS] < t)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
 
 // Evaluation pass of a lane's own window: kappa (density weights) and mu
 // (majorant weights) at its np sorted points, from every chord that contains
@@ -558,14 +564,19 @@ template <bool COUNT, class LeafFn>
 static __device__ __forceinline__ void packet_walk(const SceneView& S, const SegState& st, bool act, float ta,
                                                    const float& tb, int* __restrict__ pstk, Work& wk, LeafFn&& leaf) {
     const Seg& sg = st.sg;
-    if (S.n == 1) {
-        if (act) leaf(0);
+    auto leaves = [&](int c) {
+        int first, count;
+        leaf_range(c, &first, &count);
+        for (int k = 0; k < count; ++k) leaf(first + k);
+    };
+    if (S.croot < 0) {
+        if (act) leaves(S.croot);
         return;
     }
     const float ix = 1.0f / sg.vx, iy = 1.0f / sg.vy, iz = 1.0f / sg.vz;
     int sp = 0, node = 0;
     for (;;) {
-        const TNode* nd = S.nodes + node;
+        const TNode* nd = S.cnodes + node;
         if (COUNT && act) ++wk.nodes;
         uint32_t c = nd->cells;
         float tbn = tb;
@@ -574,11 +585,11 @@ static __device__ __forceinline__ void packet_walk(const SceneView& S, const Seg
         uint64_t bl = __ballot(hl), br = __ballot(hr);
         int lc = nd->lchild, rc = nd->rchild;
         if (bl && lc < 0) {
-            if (hl) leaf(~lc);
+            if (hl) leaves(lc);
             bl = 0;
         }
         if (br && rc < 0) {
-            if (hr) leaf(~rc);
+            if (hr) leaves(rc);
             br = 0;
         }
         if (bl && br) {
