@@ -8,10 +8,11 @@
 // with the server.
 // Scheduling: requests wait in FIFO order until their rays fit the pool; an
 // admitted request's rays are generated on the device right away.  Each step
-// assembles one batch of up to `max_tiles` tiles of `tile_rays` rays, taking
-// tiles round-robin from every admitted request, and launches it as a single
-// kernel; up to two batches are in flight, each followed by an event.  A
-// request finishes when the events of all its tiles have completed.
+// assembles one batch of up to `max_tiles` tiles of `tile_rays` rays from the
+// admitted requests, shortest remaining work first (rays left x samples,
+// multiple scattering weighted 3x), and launches it as a single kernel; up to
+// two batches are in flight, each followed by an event.  A request finishes
+// when the events of all its tiles have completed.
 // The API is single-threaded: all calls on one server come from one thread.
 #include <string.h>
 
@@ -247,6 +248,13 @@ static gf_status launch_batch(gf_server_s* S) {
     for (Req* r : S->active)
         if (r->next_ray < r->n) open.push_back(r);
     if (open.empty()) return GF_OK;
+    // shortest remaining work first (rays left x samples, multiple scattering
+    // weighted 3x), arrival order among equals: a small request that arrives
+    // behind a large one finishes in the next batch instead of after it
+    auto work = [](const Req* r) {
+        return (double)(r->n - r->next_ray) * r->q.render.spp * (r->q.render.multiple ? 3.0 : 1.0);
+    };
+    std::stable_sort(open.begin(), open.end(), [&](const Req* a, const Req* b) { return work(a) < work(b); });
     char* hreq = S->hreq[slot];
     char* htile = S->htile[slot];
     std::map<uint64_t, int> local;
@@ -255,12 +263,8 @@ static gf_status launch_batch(gf_server_s* S) {
     b.ev = S->events[slot];
     int ntiles = 0, nreq = 0;
     std::map<uint64_t, int> rays_in;
-    bool progress = true;
-    while (ntiles < S->max_tiles && progress) {
-        progress = false;
-        for (Req* r : open) {
-            if (ntiles >= S->max_tiles) break;
-            if (r->next_ray >= r->n) continue;
+    for (Req* r : open) {
+        while (ntiles < S->max_tiles && r->next_ray < r->n) {
             auto it = local.find(r->id);
             int li;
             if (it == local.end()) {
@@ -276,7 +280,6 @@ static gf_status launch_batch(gf_server_s* S) {
             r->next_ray += cnt;
             rays_in[r->id] += cnt;
             ++ntiles;
-            progress = true;
         }
     }
     for (auto& kv : rays_in) b.work.push_back(kv);

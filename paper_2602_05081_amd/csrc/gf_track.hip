@@ -36,6 +36,7 @@
 #define TS_LDS 24    // per-lane stack entries kept in LDS; deeper ones go to the workspace
 #define TK 64        // tentative points per window
 #define CQ 8         // leaf candidates a lane queues before the wave processes them
+#define SG 8         // samples whose secondary paths a lane follows back to back
 // Majorant weight cap of a stochastic cell.  It bounds the work of a path
 // that drew a heavily weighted (rarely drawn) bin; ratio tracking and the
 // signed-weight delta tracking stay unbiased where the majorant falls below
@@ -53,7 +54,9 @@
 #define WS_MAJ TK
 #define WS_XI (2 * TK)
 #define WS_SPILL (3 * TK)
-#define WS_ROWS (WS_SPILL + TR_STACK - TS_LDS)
+#define WS_TC (WS_SPILL + TR_STACK - TS_LDS)
+#define WS_WF (WS_TC + SG)
+#define WS_ROWS (WS_WF + SG)
 
 // c_i / amp_i: the density's normalisation (2 pi)^-3/2 / (s0 s1 s2) over the
 // optical-depth amplitude 1 / (4 pi s0 s1 s2), i.e. sqrt(2 / pi)
@@ -193,6 +196,8 @@ struct LaneMem {
     __device__ float& kap(int k) const { return ws[(WS_KAP + k) * TR_THREADS]; }
     __device__ float& maj(int k) const { return ws[(WS_MAJ + k) * TR_THREADS]; }
     __device__ float& xi(int k) const { return ws[(WS_XI + k) * TR_THREADS]; }
+    __device__ float& ctc(int k) const { return ws[(WS_TC + k) * TR_THREADS]; }  // camera collision of sample k
+    __device__ float& cwf(int k) const { return ws[(WS_WF + k) * TR_THREADS]; }  // its delta-tracking weight
     __device__ void push(int sp, int v) const {
         if (sp < TS_LDS)
             stk[sp * TR_THREADS] = v;
@@ -766,13 +771,15 @@ static __device__ bool track_own(const SceneView& S, const MaskView& M, SegState
 // for its transmittance on the same tentative points); a real collision
 // scatters isotropically and ratio-tracks the way out.  Multiple scattering:
 // delta tracking from segment to segment with Henyey-Greenstein scattering
-// until escape or max_scatter scatterings.
+// until escape or max_scatter scatterings.  The camera segment draws from
+// the sample's stream (seed, ray, sample, 0), the rest of its path from
+// (seed, ray, sample, 2).
 struct RenderLane {
     const float* r;
     uint32_t key;
     int nsc, seg;
     bool shadow;
-    float w, L, Tp;
+    float w, L;
     float s1, s2, q1, q2;
     Rng g;
     SegState st;
@@ -781,27 +788,44 @@ struct RenderLane {
         key = k;
         s1 = s2 = q1 = q2 = 0.0f;
     }
+    // camera segment of sample s
     __device__ void start(const SceneView& S, const MaskView& M, const RenderArgs& A, int s) {
         g.init(A.seed, key, (uint32_t)s, 0u);
-        w = 1.0f;
-        L = 0.0f;
-        Tp = 1.0f;
-        nsc = seg = 0;
-        shadow = false;
         CellW cw = A.stochastic ? stochastic_weights(S, r[3], r[4], r[5], g) : fixed_weights(M);
         begin_segment(S, st, r, r + 3, r[6], r[7], cw, MODE_RATIO | MODE_DELTA, g);
+    }
+    // after the camera segment: its transmittance estimate
+    __device__ void camera_done() {
+        q1 += st.T;
+        q2 += st.T * st.T;
+    }
+    // the rest of sample s from its camera outcome (collision distance tc,
+    // weight factor wf); true when the sample is already over
+    __device__ bool begin_path(const SceneView& S, const MaskView& M, const RenderArgs& A, int s, float tc,
+                               float wf) {
+        g.init(A.seed, key, (uint32_t)s, 2u);
+        w = 1.0f;
+        L = 0.0f;
+        nsc = seg = 0;
+        shadow = false;
+        st.sg.ox = r[0];
+        st.sg.oy = r[1];
+        st.sg.oz = r[2];
+        st.sg.vx = r[3];
+        st.sg.vy = r[4];
+        st.sg.vz = r[5];
+        st.tc = tc;
+        st.wf = wf;
+        return segment_done(S, M, A);
     }
     __device__ bool end_sample() {
         s1 += L;
         s2 += L * L;
-        q1 += Tp;
-        q2 += Tp * Tp;
         return true;
     }
     // the current segment is finished: scatter (and set up the next
     // segment) or close the sample; true when the sample is over
     __device__ bool segment_done(const SceneView& S, const MaskView& M, const RenderArgs& A) {
-        if (seg == 0) Tp = st.T;
         if (shadow) {
             L += w * A.albedo * st.T * A.env;
             return end_sample();
@@ -841,9 +865,11 @@ struct RenderLane {
     }
 };
 
-// One wave renders 64 rays (idx < 0: no ray on this lane): for every sample
-// the camera segments go through the packet passes together, then each lane
-// follows its own path with per-lane passes.
+// One wave renders 64 rays (idx < 0: no ray on this lane), SG samples at a
+// time: the camera segments of each sample go through the packet passes
+// together (their outcomes kept in the workspace), then every lane follows
+// the paths of its SG samples back to back with per-lane passes, so a lane
+// with short paths does not wait on the longest path of each sample.
 template <bool COUNT>
 static __device__ void render_rays(const SceneView& S, const MaskView& M, const RenderArgs& A,
                                    const float* __restrict__ rays, int idx, const LaneMem& lm, int* pstk, Work& wk,
@@ -851,12 +877,30 @@ static __device__ void render_rays(const SceneView& S, const MaskView& M, const 
     const bool valid = idx >= 0;
     RenderLane rl;
     if (valid) rl.begin(rays + (size_t)idx * 8, (uint32_t)idx);
-    for (int s = 0; s < A.spp; ++s) {
-        if (valid) rl.start(S, M, A, s);
-        track_camera<COUNT>(S, M, rl.st, valid, lm, pstk, wk);
-        bool more = valid && !rl.segment_done(S, M, A);
+    for (int s0 = 0; s0 < A.spp; s0 += SG) {
+        const int gn = min(SG, A.spp - s0);
+        for (int k = 0; k < gn; ++k) {
+            if (valid) rl.start(S, M, A, s0 + k);
+            track_camera<COUNT>(S, M, rl.st, valid, lm, pstk, wk);
+            if (valid) {
+                rl.camera_done();
+                lm.ctc(k) = rl.st.tc;
+                lm.cwf(k) = rl.st.wf;
+            }
+        }
+        int k = 0;
+        // the next sample of the group whose path goes on past the camera
+        auto next = [&]() {
+            while (k < gn) {
+                bool over = rl.begin_path(S, M, A, s0 + k, lm.ctc(k), lm.cwf(k));
+                ++k;
+                if (!over) return true;
+            }
+            return false;
+        };
+        bool more = valid && next();
         while (__any(more)) {
-            if (more && track_own<COUNT>(S, M, rl.st, lm, wk)) more = !rl.segment_done(S, M, A);
+            if (more && track_own<COUNT>(S, M, rl.st, lm, wk) && rl.segment_done(S, M, A)) more = next();
         }
     }
     if (valid) rl.result(A, out4);
