@@ -19,6 +19,9 @@ The draw order is fixed (one ``numpy.random.Generator(PCG64(seed))``, every
 quantity drawn in float64, then cast to float32 at the end):
 
     [blob field parameters]  mu  q  s  f-direction  f-magnitude  phi  alpha
+
+after which every fourth primitive (index % 4 == 0) is turned into a Gaussian
+of the low-pass level: f = 0, phi = 0, s scaled by 1.5 and alpha by 4.
 """
 from __future__ import annotations
 
@@ -26,6 +29,7 @@ import numpy as np
 
 N_FIELDS = 15
 MU, Q, S, F, PHI, ALPHA = slice(0, 3), slice(3, 7), slice(7, 10), slice(10, 13), 13, 14
+GAUSS_EVERY, GAUSS_SCALE, GAUSS_WEIGHT = 4, 1.5, 4.0
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -44,6 +48,16 @@ def _common_tail(g: np.random.Generator, mu: np.ndarray, smin: float, smax: floa
     fmag = g.uniform(0.0, 1.0, size=n) / s.min(axis=1)
     phi = g.uniform(0.0, 2.0 * np.pi, size=n)
     alpha = g.lognormal(0.0, 0.5, size=n)
+    # the pyramid's low-pass level (Sec. 4): every fourth primitive is a
+    # zero-frequency kernel (a Gaussian) with 1.5x the scales and 4x the
+    # weight, so that the mixture is positive almost everywhere and the Gabor
+    # kernels are residuals on top of it
+    base = np.arange(n) % GAUSS_EVERY == 0
+    s[base] *= GAUSS_SCALE
+    fdir[base] = 0.0
+    fmag[base] = 0.0
+    phi[base] = 0.0
+    alpha[base] *= GAUSS_WEIGHT
     out = np.empty((n, N_FIELDS), dtype=np.float64)
     out[:, MU] = mu
     out[:, Q] = q

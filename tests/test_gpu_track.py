@@ -22,6 +22,17 @@ def _pooled(a, b, se):
     return abs(np.sum(a - b)) / np.sqrt(np.sum(se ** 2)), np.max(np.abs(a - b) / se)
 
 
+def _check_ratio(Tm, Tv, tau, spp, min_ok):
+    """Ratio-tracking means against exp(-tau).  Deep rays (spp exp(-tau) < 5)
+    end at zero in nearly every sample, so their sample variance is no
+    standard error: they only get an absolute bound."""
+    ok = spp * np.exp(-tau) >= 5.0
+    assert ok.sum() >= min_ok
+    pooled, worst = _pooled(Tm[ok], np.exp(-tau[ok]), np.sqrt(Tv[ok] / spp))
+    assert pooled < 3.0 and worst < 5.0
+    assert np.all(np.abs(Tm[~ok] - np.exp(-tau[~ok])) < 2e-3)
+
+
 def test_density_and_majorant():
     gf = require_gpu()
     params, rho = W.scene("tiny256"), W.rho("tiny256")
@@ -53,8 +64,7 @@ def test_ratio_tracking_mean_is_exp_minus_tau():
     Tm, Tv = gf.gf_transmittance_ratio(scene, dev(sub), spp, seed=11)
     Tm, Tv = host(Tm), host(Tv)
     tau, _, hits = oracle.tau(params, sub, rho=rho)
-    pooled, worst = _pooled(Tm, np.exp(-tau), np.sqrt(Tv / spp))
-    assert pooled < 3.0 and worst < 5.0
+    _check_ratio(Tm, Tv, tau, spp, min_ok=450)
     assert np.all(Tm[hits == 0] == 1.0)
     # the workload's own output: 16 samples over the whole 64x64 frame
     T16, _ = gf.gf_transmittance_ratio(scene, dev(rays), 16, seed=1, image_width=64)
@@ -69,8 +79,7 @@ def test_ratio_tracking_masks():
     for cells in (gf.gf_mask_lod_cells(2), 0):
         Tm, Tv = gf.gf_transmittance_ratio(scene, dev(rays), spp, seed=3, mask=gf.make_mask(cells))
         tau, _, _ = oracle.tau(params, rays, rho=rho, cells=cells)
-        pooled, worst = _pooled(host(Tm), np.exp(-tau), np.sqrt(host(Tv) / spp))
-        assert pooled < 3.0 and worst < 5.0
+        _check_ratio(host(Tm), host(Tv), tau, spp, min_ok=200)
 
 
 def _render_pair(params, rays, rho, spp_gpu, spp_orc, **kw):

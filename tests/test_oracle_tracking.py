@@ -15,8 +15,9 @@ import pytest
 import scipy.stats as st
 
 import gen
+from gen import workloads as W
 
-RHO_TINY = 0.01655701747503121
+RHO_TINY = W.rho("tiny256")
 
 
 def test_philox_known_answers(orc):
@@ -94,7 +95,11 @@ def test_weighted_delta_tracking_escape_signed(orc):
     tau, _, _ = orc.tau(params, rays, rho=RHO_TINY)
     t, w = orc.free_flight(params, rays, spp, seed=9, rho=RHO_TINY)
     est = np.where(np.isfinite(t), 0.0, w)
-    pooled, worst = _pooled(est.mean(axis=1), np.exp(-tau), est.std(axis=1, ddof=1) / math.sqrt(spp))
+    # rays whose expected number of escapes is below 5 cannot estimate their
+    # own standard error (all samples collide), so they are left out
+    ok = spp * np.exp(-tau) >= 5.0
+    assert ok.sum() >= 30
+    pooled, worst = _pooled(est.mean(axis=1)[ok], np.exp(-tau[ok]), est.std(axis=1, ddof=1)[ok] / math.sqrt(spp))
     assert pooled < 3.0 and worst < 4.5
 
 
