@@ -20,8 +20,9 @@ quantity drawn in float64, then cast to float32 at the end):
 
     [blob field parameters]  mu  q  s  f-direction  f-magnitude  phi  alpha
 
-after which every fourth primitive (index % 4 == 0) is turned into a Gaussian
-of the low-pass level: f = 0, phi = 0, s scaled by 1.5 and alpha by 4.
+after which, in blob scenes only, every fourth primitive (index % 4 == 0) is
+turned into a Gaussian of the low-pass level: f = 0, phi = 0, alpha scaled by 4.
+Uniform scenes are Gabor kernels only (a zero-mean signed field).
 """
 from __future__ import annotations
 
@@ -29,14 +30,15 @@ import numpy as np
 
 N_FIELDS = 15
 MU, Q, S, F, PHI, ALPHA = slice(0, 3), slice(3, 7), slice(7, 10), slice(10, 13), 13, 14
-GAUSS_EVERY, GAUSS_SCALE, GAUSS_WEIGHT = 4, 1.5, 4.0
+GAUSS_EVERY, GAUSS_WEIGHT = 4, 4.0
 
 
 def _rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def _common_tail(g: np.random.Generator, mu: np.ndarray, smin: float, smax: float) -> np.ndarray:
+def _common_tail(g: np.random.Generator, mu: np.ndarray, smin: float, smax: float,
+                 base_level: bool = False) -> np.ndarray:
     n = mu.shape[0]
     q = g.standard_normal((n, 4))
     q /= np.linalg.norm(q, axis=1, keepdims=True)
@@ -48,16 +50,16 @@ def _common_tail(g: np.random.Generator, mu: np.ndarray, smin: float, smax: floa
     fmag = g.uniform(0.0, 1.0, size=n) / s.min(axis=1)
     phi = g.uniform(0.0, 2.0 * np.pi, size=n)
     alpha = g.lognormal(0.0, 0.5, size=n)
-    # the pyramid's low-pass level (Sec. 4): every fourth primitive is a
-    # zero-frequency kernel (a Gaussian) with 1.5x the scales and 4x the
-    # weight, so that the mixture is positive almost everywhere and the Gabor
-    # kernels are residuals on top of it
-    base = np.arange(n) % GAUSS_EVERY == 0
-    s[base] *= GAUSS_SCALE
-    fdir[base] = 0.0
-    fmag[base] = 0.0
-    phi[base] = 0.0
-    alpha[base] *= GAUSS_WEIGHT
+    if base_level:
+        # the pyramid's low-pass level (Sec. 4): every fourth primitive is a
+        # zero-frequency kernel (a Gaussian) with 4x the weight, so that the
+        # mixture is positive almost everywhere and the Gabor kernels are
+        # residuals on top of it
+        base = np.arange(n) % GAUSS_EVERY == 0
+        fdir[base] = 0.0
+        fmag[base] = 0.0
+        phi[base] = 0.0
+        alpha[base] *= GAUSS_WEIGHT
     out = np.empty((n, N_FIELDS), dtype=np.float64)
     out[:, MU] = mu
     out[:, Q] = q
@@ -82,6 +84,7 @@ def blob_scene(n: int, seed: int, smin: float = 0.003, smax: float = 0.05, n_blo
     [0.03, 0.15], blob weights uniform in [0.5, 1.5].  A mean is drawn by picking
     a blob with probability proportional to its weight and adding an isotropic
     normal offset of the blob's radius; means outside the unit cube are redrawn.
+    Every fourth primitive belongs to the Gaussian low-pass level.
     """
     g = _rng(seed)
     centres = g.uniform(0.15, 0.85, size=(n_blobs, 3))
@@ -96,7 +99,7 @@ def blob_scene(n: int, seed: int, smin: float = 0.003, smax: float = 0.05, n_blo
         ok = np.all((cand >= 0.0) & (cand <= 1.0), axis=1)
         mu[todo[ok]] = cand[ok]
         todo = todo[~ok]
-    return _common_tail(g, mu, smin, smax)
+    return _common_tail(g, mu, smin, smax, base_level=True)
 
 
 def jitter_scene(params: np.ndarray, seed: int, rel: float = 0.05) -> np.ndarray:
