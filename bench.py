@@ -237,10 +237,13 @@ def serving(args, gf, W, np, torch):
     qps = 0.7 * plain_rate
     arrivals = gen.poisson_arrivals(n, qps, seed=6)
     log("serving: plain renderer saturates at %.3f requests/s; replaying %d requests at %.3f/s" % (plain_rate, n, qps))
+    def done(tag):
+        return lambda k, t: log("serving (%s): request %d done at %.1f s" % (tag, k, t))
+
     lat_s, mk_s, _, held = serve.run_server(scenes, reqs, arrivals, mem_budget=1 << 30, tile_rays=4096,
-                                            max_tiles=96, time_limit=600)
+                                            max_tiles=96, time_limit=600, on_done=done("batching"))
     log("serving: continuous batching done in %.1f s" % mk_s)
-    lat_p, mk_p, _ = serve.run_plain(scenes, reqs, arrivals, time_limit=600)
+    lat_p, mk_p, _ = serve.run_plain(scenes, reqs, arrivals, time_limit=600, on_done=done("plain"))
     log("serving: plain renderer done in %.1f s" % mk_p)
     out = {"qps": round(qps, 2), "requests": n, "scenes": W.SERVE_SCENES,
            "continuous_batching": serve.summarize(lat_s, mk_s, reqs),

@@ -34,9 +34,10 @@ def _percentiles(lat):
 
 
 def run_server(scenes, reqs, arrivals, mem_budget=512 << 20, tile_rays=4096, max_tiles=64, outputs=None,
-               time_limit=None):
+               time_limit=None, on_done=None):
     """Replays the trace in wall-clock time.  Returns (latencies, makespan,
-    outputs, max bytes held)."""
+    outputs, max bytes held).  on_done(k, seconds) is called as request k
+    completes."""
     srv = _lib.Server(mem_budget, tile_rays, max_tiles)
     outs = outputs if outputs is not None else [torch.empty(r["res"] * r["res"], device="cuda") for r in reqs]
     torch.cuda.synchronize()
@@ -55,6 +56,8 @@ def run_server(scenes, reqs, arrivals, mem_budget=512 << 20, tile_rays=4096, max
         srv.step(wait=False)
         for rid in srv.poll():
             t_done[id2k[rid]] = time.perf_counter() - t0
+            if on_done:
+                on_done(id2k[rid], t_done[id2k[rid]])
         max_held = max(max_held, srv.stats()[2])
         if nxt < len(reqs) and srv.stats()[1] == 0 and srv.stats()[0] == 0:
             time.sleep(max(0.0, min(0.001, arrivals[nxt] - (time.perf_counter() - t0))))
@@ -67,8 +70,9 @@ def run_server(scenes, reqs, arrivals, mem_budget=512 << 20, tile_rays=4096, max
     return lat, makespan, outs, max_held
 
 
-def run_plain(scenes, reqs, arrivals, outputs=None, time_limit=None):
-    """FIFO plain renderer: each request rendered alone, in arrival order."""
+def run_plain(scenes, reqs, arrivals, outputs=None, time_limit=None, on_done=None):
+    """FIFO plain renderer: each request rendered alone, in arrival order.
+    on_done(k, seconds) is called as request k completes."""
     outs = outputs if outputs is not None else [torch.empty(r["res"] * r["res"], device="cuda") for r in reqs]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -82,6 +86,8 @@ def run_plain(scenes, reqs, arrivals, outputs=None, time_limit=None):
         outs[k].copy_(L)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0 - arrivals[k])
+        if on_done:
+            on_done(k, time.perf_counter() - t0)
         if time_limit and time.perf_counter() - t0 > time_limit:
             raise TimeoutError("plain trace exceeded %.0f s" % time_limit)
     return lat, time.perf_counter() - t0, outs
