@@ -956,10 +956,13 @@ void or_hg_cos(double g, int64_t n, uint64_t seed, double* out)
 }
 
 /* Per-segment stochastic mask (uniform + control variate over levels,
- * importance sampling over orientation bins): level 0 always with weight 1;
- * level l in {1,2,3} with probability 1/3; bin k with probability w_k / W,
- * w_k = exp(-fbar_{l,k}^2 a_k^2 / 2), a_k = |v.e_k|; the drawn cell gets
- * weight 3 W / w_k. */
+ * orientation bins drawn from an even mixture of importance and uniform
+ * sampling, Appendix B tables): level 0 always with weight 1; level l in
+ * {1,2,3} with probability 1/3; bin k with probability
+ * p_k = w_k / (2 W) + 1/6, w_k = exp(-fbar_{l,k}^2 a_k^2 / 2), a_k = |v.e_k|,
+ * W = sum_k w_k; the drawn cell gets weight 3 / p_k (at most 18).  The w_k
+ * are scaled by their maximum first (p_k does not change) so that W never
+ * underflows. */
 static void stochastic_weights(const int32_t* cell, int64_t n, const double* med12, const double* v, rng_t* g,
                                double* wt)
 {
@@ -967,17 +970,23 @@ static void stochastic_weights(const int32_t* cell, int64_t n, const double* med
     double ul = rng_u(g), ub = rng_u(g);
     int l = 1 + (int)(ul * 3.0);
     if (l > 3) l = 3;
-    double wk[3], W = 0.0;
+    double lw[3], mx = -HUGE_VAL;
     for (int k = 0; k < 3; ++k) {
         double a = fabs(v[k]) / vn, fb = med12[l * 3 + k];
-        wk[k] = exp(-0.5 * fb * fb * a * a);
+        lw[k] = -0.5 * fb * fb * a * a;
+        if (lw[k] > mx) mx = lw[k];
+    }
+    double wk[3], W = 0.0, pk[3];
+    for (int k = 0; k < 3; ++k) {
+        wk[k] = exp(lw[k] - mx);
         W += wk[k];
     }
+    for (int k = 0; k < 3; ++k) pk[k] = 0.5 * wk[k] / W + 1.0 / 6.0;
     int k = 0;
-    double acc = wk[0] / W;
-    while (k < 2 && ub >= acc) { ++k; acc += wk[k] / W; }
+    double acc = pk[0];
+    while (k < 2 && ub >= acc) { ++k; acc += pk[k]; }
     int pick = l * 3 + k;
-    double wpick = 3.0 * W / wk[k];
+    double wpick = 3.0 / pk[k];
     for (int64_t i = 0; i < n; ++i) wt[i] = (cell[i] < 3) ? 1.0 : (cell[i] == pick ? wpick : 0.0);
 }
 

@@ -37,11 +37,10 @@
 #define TK 64        // tentative points per window
 #define CQ 8         // leaf candidates a lane queues before the wave processes them
 #define SG 8         // samples whose secondary paths a lane follows back to back
-// Majorant weight cap of a stochastic cell.  It bounds the work of a path
-// that drew a heavily weighted (rarely drawn) bin; ratio tracking and the
-// signed-weight delta tracking stay unbiased where the majorant falls below
-// |kappa| (only their variance grows).
-#define MAJ_CAP 16.0f
+// Largest weight of a stochastic cell (3 / p_k with p_k >= 1/6): the
+// majorant's multiplier of the drawn cell never needs to exceed it, so the
+// majorant bounds |kappa| of the reweighted field too.
+#define MAJ_CAP 18.0f
 // Hard bound on windows per segment (TK points each): a segment that would
 // need more is cut short there, which keeps every wave's work finite.
 #define MAX_WINDOWS 4096
@@ -80,10 +79,11 @@ static __device__ __forceinline__ CellW fixed_weights(const MaskView& M) {
     return cw;
 }
 
-// Uniform + control variate over levels, importance sampling over bins:
-// level 0 keeps weight 1; one level l in 1..3 (probability 1/3) and one bin k
-// (probability w_k / W, w_k = exp(-m_lk^2 a_k^2 / 2), a_k = |v_k| / |v|) get
-// weight 3 W / w_k; every other cell weight 0.
+// Uniform + control variate over levels; over bins an even mixture of the
+// importance and uniform strategies (Appendix B tables): level 0 keeps
+// weight 1; one level l in 1..3 (probability 1/3) and one bin k (probability
+// p_k = w_k / (2W) + 1/6, w_k = exp(-m_lk^2 a_k^2 / 2), a_k = |v_k| / |v|)
+// get weight 3 / p_k <= 18; every other cell weight 0.
 static __device__ __forceinline__ CellW stochastic_weights(const SceneView& S, float vx, float vy, float vz, Rng& g) {
     float ul = g.u(), ub = g.u();
     int l = 1 + (int)(ul * 3.0f);
@@ -102,19 +102,22 @@ static __device__ __forceinline__ CellW stochastic_weights(const SceneView& S, f
         wk[k] = __expf(lw[k] - mx);
         W += wk[k];
     }
-    // inverse CDF over bins with non-zero weight
-    int k = -1;
-    float acc = 0.0f, target = ub * W;
-    for (int j = 0; j < 3; ++j) {
-        if (wk[j] <= 0.0f) continue;
-        k = j;
-        acc += wk[j];
-        if (target < acc) break;
+    // even mixture of importance and uniform sampling: p_k >= 1/6
+    float p[3];
+    for (int k = 0; k < 3; ++k) p[k] = 0.5f * wk[k] / W + (1.0f / 6.0f);
+    int k = 2;
+    float acc = 0.0f;
+    for (int j = 0; j < 2; ++j) {
+        acc += p[j];
+        if (ub < acc) {
+            k = j;
+            break;
+        }
     }
     CellW cw;
     cw.pick = 3 * l + k;
     cw.cells = 0x7u | (1u << cw.pick);
-    cw.wp = 3.0f * W / wk[k];
+    cw.wp = 3.0f / p[k];
     cw.mwp = fminf(cw.wp, MAJ_CAP);
     return cw;
 }

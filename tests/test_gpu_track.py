@@ -140,9 +140,10 @@ def test_stochastic_primary_transmittance_exact_expectation():
         e, mx = 0.0, 0.0
         for l in (1, 2, 3):
             w = np.exp(-0.5 * med[3 * l:3 * l + 3] ** 2 * np.abs(v) ** 2)
+            p = 0.5 * w / w.sum() + 1.0 / 6.0
             for k in range(3):
-                t = sum(tc[0:3]) + 3 * w.sum() / w[k] * tc[3 * l + k]
-                e += w[k] / w.sum() / 3 * math.exp(-t)
+                t = sum(tc[0:3]) + 3 / p[k] * tc[3 * l + k]
+                e += p[k] / 3 * math.exp(-t)
                 mx = max(mx, abs(t))
         exact.append(e)
         keep.append(mx < 0.6)

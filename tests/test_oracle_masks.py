@@ -79,9 +79,9 @@ def _stoch_table(orc, params, ray, rho):
     out = []
     for l in (1, 2, 3):
         w = np.exp(-0.5 * med[3 * l:3 * l + 3] ** 2 * np.abs(v) ** 2)
-        W = w.sum()
+        p = 0.5 * w / w.sum() + 1.0 / 6.0  # even mixture of importance and uniform bin sampling
         for k in range(3):
-            out.append((w[k] / W / 3.0, tau_L0 + 3.0 * W / w[k] * tc[3 * l + k]))
+            out.append((p[k] / 3.0, tau_L0 + 3.0 / p[k] * tc[3 * l + k]))
     return out, sum(tc)
 
 
