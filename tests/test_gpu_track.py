@@ -193,3 +193,58 @@ def test_render_full_size_sampled_blob100k():
     worst = np.max(np.abs(g - o) / se)
     print("pooled %.2f worst %.2f" % (pooled, worst), flush=True)
     assert pooled < 3.0 and worst < 6.0
+
+
+def _stochastic_expectation(params, rays, rho, med):
+    """E[T_hat] of the stochastic primary transmittance, summed exactly over
+    the per-segment mask distribution: level 0 always, level l in 1..3 with
+    probability 1/3, bin k with p_k = w_k/(2W) + 1/6 and weight 3/p_k."""
+    tcs = np.stack([oracle.tau(params, rays, rho=rho, cells=1 << c)[0] for c in range(12)], axis=1)
+    out = []
+    for ray, tc in zip(rays, tcs):
+        v = ray[3:6] / np.linalg.norm(ray[3:6])
+        e = 0.0
+        for l in (1, 2, 3):
+            w = np.exp(-0.5 * med[3 * l:3 * l + 3] ** 2 * np.abs(v) ** 2)
+            p = 0.5 * w / w.sum() + 1.0 / 6.0
+            for k in range(3):
+                e += p[k] / 3 * math.exp(-(sum(tc[0:3]) + 3 / p[k] * tc[3 * l + k]))
+        out.append(e)
+    return np.array(out)
+
+
+def test_render_full_size_multiple_stochastic_blob1m():
+    """1M primitives, 1024-wide frame, 4 spp, multiple scattering (HG 0.3,
+    albedo 0.9, up to 16 bounces) with per-segment stochastic masks: a
+    32-row band of the frame in its launch shape, then the primary
+    transmittance of sampled pixels against its exact expectation over the
+    mask distribution (oracle optical depths per cell)."""
+    gf = require_gpu()
+    params, rays, rho = W.scene("blob1m"), W.rays("blob1m"), W.rho("blob1m")
+    scene = gf.Scene(dev(params), rho=rho)
+    band = rays[496 * 1024:528 * 1024]
+    d = gf.render_desc(spp=4, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, stochastic=True, seed=41)
+    L, Lv, T, Tv = (host(x) for x in gf.gf_render(scene, dev(band), d, image_width=1024))
+    print("band done: mean L %.4f, mean T %.4f" % (L.mean(), T.mean()), flush=True)
+    assert np.all(np.isfinite(L)) and np.all(np.isfinite(T))
+    assert np.all(np.isfinite(Lv)) and np.all(np.isfinite(Tv))
+    # sampled pixels with many samples: a lane runs all samples of its ray,
+    # so each pixel's ray is repeated (every copy has its own streams) and
+    # the copies' 4-sample means are pooled
+    sub = W.pixel_subset(band.shape[0], k=24, seed=23)
+    rs = band[sub]
+    copies = 512
+    d = gf.render_desc(spp=4, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, stochastic=True, seed=43)
+    _, _, Tc, _ = (host(x) for x in gf.gf_render(scene, dev(np.repeat(rs, copies, axis=0)), d))
+    Tc = Tc.reshape(len(rs), copies)
+    spp = 4 * copies
+    Tm, Tv = Tc.mean(axis=1), Tc.var(axis=1, ddof=1) * 4
+    print("sampled pixels done", flush=True)
+    med = np.array(scene.info().cell_median_kw[:], dtype=np.float64)
+    exact = _stochastic_expectation(params, rs, rho, med)
+    ok = spp * exact >= 5.0
+    assert ok.sum() >= 8
+    pooled, worst = _pooled(Tm[ok], exact[ok], np.sqrt(Tv[ok] / spp))
+    print("pooled %.2f worst %.2f over %d pixels" % (pooled, worst, ok.sum()), flush=True)
+    assert pooled < 3.0 and worst < 5.0
+    assert np.all(np.abs(Tm[~ok] - exact[~ok]) < 2e-3)
