@@ -136,11 +136,16 @@ gf_status gf_optical_depth_counts(gf_scene scene, const float* rays, int64_t n, 
 gf_status gf_density(gf_scene scene, const float* pts, int64_t n, gf_mask mask, float* kappa, float* kbar,
                      void* stream);
 
-/* Ratio-tracking transmittance with the majorant grid: spp estimates per ray
- * T_hat = prod_j (1 - kappa(x_j)/kbar_j); outputs the mean and the unbiased
- * sample variance (T_var may be NULL).  Random numbers: Philox4x32-10 keyed by
- * seed, counter (ray, sample, block, stream); image_width as for
- * gf_optical_depth.  The scene's LBVH depth must not exceed 64 (checked). */
+/* Ratio-tracking transmittance (Sec. 4.4 distance sampling; ratio tracking
+ * of the voxel comparison): spp estimates per ray T_hat = prod_j (1 -
+ * kappa(x_j)/kbar(x_j)) over tentative points of the per-ray envelope
+ * majorant kbar(t) = sum_i rho |alpha_i| c_i exp(-M_i/2) of the masked
+ * primitives the ray crosses (it bounds |kappa| term by term); outputs the
+ * mean and the unbiased sample variance (T_var may be NULL).  Random
+ * numbers: Philox4x32-10 streams keyed by (seed, ray, sample) and per chord
+ * by (primitive, window, block); image_width as for gf_optical_depth.  The
+ * scene's LBVH depth must not exceed 64 (checked).  Each ray's samples run
+ * on one lane: for many samples of few rays, repeat the rays. */
 gf_status gf_transmittance_ratio(gf_scene scene, const float* rays, int64_t n, int image_width, gf_mask mask,
                                  int spp, uint64_t seed, float* T_mean, float* T_var, void* stream);
 
@@ -156,14 +161,17 @@ typedef struct {
     uint64_t seed;
 } gf_render_desc;
 
-/* Radiance per ray with weighted delta tracking (free flights) and ratio
- * tracking (shadow ray of single scattering; primary transmittance), both on
- * the majorant grid.  Single: escape -> w env; real collision -> w albedo
- * T_ratio(x, isotropic direction) env.  Multiple: free flights with albedo and
- * HG scattering until escape.  Stochastic masks: each segment keeps level 0
- * (weight 1) and draws one level l in 1..3 uniformly and one bin k with
- * probability w_k / W, w_k = exp(-m_lk^2 a_k^2 / 2), a_k = |v.e_k|,
- * m_lk = cell median of |k_W|; the drawn cell gets weight 3 W / w_k.
+/* Radiance per ray with signed-weight delta tracking (free flights) and
+ * ratio tracking (shadow ray of single scattering; primary transmittance),
+ * both against the per-ray envelope majorant of gf_transmittance_ratio.
+ * Single: escape -> w env; real collision -> w albedo T_ratio(x, isotropic
+ * direction) env.  Multiple: free flights with albedo and HG scattering until
+ * escape.  Stochastic masks (Sec. 4.5.1-4.5.2, Appendix B tables): each
+ * segment keeps level 0 (weight 1) and draws one level l in 1..3 uniformly
+ * and one bin k with probability p_k = w_k / (2W) + 1/6 (an even mixture of
+ * importance and uniform sampling), w_k = exp(-m_lk^2 a_k^2 / 2),
+ * a_k = |v.e_k|, W = sum_k w_k, m_lk = cell median of |k_W|; the drawn cell
+ * gets weight 3 / p_k (at most 18).
  * Outputs (device n, variances/T may be NULL): L mean / variance over spp,
  * primary-segment ratio-tracked transmittance mean / variance.
  * image_width as for gf_optical_depth.  Each ray's samples are traced by one
