@@ -3,8 +3,11 @@
     python profiles/summarize.py stats <kernel_stats.csv> <out.txt> "<command>"
     python profiles/summarize.py pmc <fetch_counter_collection.csv> <write_counter_collection.csv> <out.txt> \
         "<fetch command>" "<write command>" <calibration bytes>
+    python profiles/summarize.py counters <counter_collection.csv> <out.txt> "<command>"
 
 `stats` keeps each kernel's call count, total and average duration.
+`counters` keeps, per kernel, the average per dispatch of every counter of
+one --pmc pass.
 `pmc` keeps, per kernel, the average FETCH_SIZE and WRITE_SIZE per dispatch (KiB)
 and the scale factors read off the calibration launches bench.py makes with
 --copy-calibration: a 1 GiB fill (written bytes) and a 1 GiB device copy
@@ -71,8 +74,30 @@ def pmc(fsrc, wsrc, out, fcmd, wcmd, calib_bytes):
                                                            (f * ffac + w * wfac) * 1024 / 1e6))
 
 
+def counters(src, out, cmd):
+    acc = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    names = []
+    for r in csv.DictReader(open(src)):
+        k, c = r["Kernel_Name"], r["Counter_Name"]
+        acc[k][c] += float(r["Counter_Value"])
+        disp[k].add(r["Dispatch_Id"])
+        if c not in names:
+            names.append(c)
+    kernels = sorted(acc, key=lambda k: -sum(acc[k].values()) / len(disp[k]))
+    with open(out, "w") as fh:
+        fh.write("# rocprofv3 --pmc summary (average per dispatch)\n# command: %s\n" % cmd)
+        fh.write("# source hash: %s\n" % source_hash())
+        fh.write("%-48s %6s" % ("kernel", "calls") + "".join(" %16s" % c for c in names) + "\n")
+        for k in kernels[:12]:
+            n = len(disp[k])
+            fh.write("%-48s %6d" % (k[:48], n) + "".join(" %16.4g" % (acc[k][c] / n) for c in names) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], sys.argv[4])
     else:
         pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], sys.argv[7])
