@@ -224,7 +224,7 @@ typedef struct {
  * once (each request holds width*height*32 bytes of rays while in flight).
  * tile_rays: rays per tile; max_tiles: tiles per device batch.  The server
  * also allocates, once, the tracking workspace of one batch (at most
- * 3072 x 59 KB).  GF_ENOMEM / GF_EDEVICE if an allocation fails. */
+ * 3072 x 62 KB).  GF_ENOMEM / GF_EDEVICE if an allocation fails. */
 gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_tiles, void* stream, gf_server* out);
 gf_status gf_server_destroy(gf_server server);
 /* Queues a request (non-blocking); *id receives its id.  GF_EINVAL if it can
@@ -240,6 +240,22 @@ gf_status gf_server_step(gf_server server, int wait);
 gf_status gf_server_poll(gf_server server, uint64_t* ids, int max, int* n_done);
 /* Requests queued, in flight, and device bytes currently held. */
 gf_status gf_server_stats(gf_server server, int* queued, int* in_flight, size_t* bytes_held);
+/* The server's scheduling policy on a virtual clock, without a device (the
+ * serving workload: requests of uneven size admitted by memory and batched
+ * as they arrive).  Request i (host arrays of n entries: width, height, spp,
+ * multiple != 0) arrives at arrival_s[i] (sorted ascending).  Each step
+ * retires the batches whose end has passed, admits queued requests in
+ * arrival order while width*height*32 bytes (256 B aligned) fit a first-fit
+ * pool of mem_budget bytes, and plans batches exactly as gf_server_step does
+ * while fewer than two are in flight; a batch starts when the previous one
+ * ends and takes sum over its tiles of rays x spp x (3 if multiple) divided
+ * by work_per_s seconds.  Outputs (host, n): admit_s[i], done_s[i]; and the
+ * largest number of pool bytes held at once (may be NULL).  GF_EINVAL for
+ * invalid sizes, unsorted arrivals or a request larger than the budget. */
+gf_status gf_server_simulate(size_t mem_budget, int tile_rays, int max_tiles, int64_t n, const int32_t* width,
+                             const int32_t* height, const int32_t* spp, const int32_t* multiple,
+                             const double* arrival_s, double work_per_s, double* admit_s, double* done_s,
+                             size_t* max_held);
 
 const char* gf_last_error(void);
 

@@ -79,6 +79,8 @@ _SIGS = {
     "gf_server_step": [_vp, _i],
     "gf_server_poll": [_vp, C.POINTER(_u64), _i, C.POINTER(_i)],
     "gf_server_stats": [_vp, C.POINTER(_i), C.POINTER(_i), C.POINTER(C.c_size_t)],
+    "gf_server_simulate": [C.c_size_t, _i, _i, _i64, _vp, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp,
+                           C.POINTER(C.c_size_t)],
 }
 
 
@@ -336,3 +338,22 @@ class Server:
 
 def gf_server_create(mem_budget, tile_rays=4096, max_tiles=64) -> Server:
     return Server(mem_budget, tile_rays, max_tiles)
+
+
+def gf_server_simulate(mem_budget: int, tile_rays: int, max_tiles: int, width, height, spp, multiple, arrival_s,
+                       work_per_s: float):
+    """The server's admission and batching policy on a virtual clock (host
+    only, no device).  Returns (admit_s, done_s, max_bytes_held) as numpy
+    arrays and an int."""
+    import numpy as np
+
+    i32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.int32))  # noqa: E731
+    w, h, s, m = i32(width), i32(height), i32(spp), i32(multiple)
+    arr = np.ascontiguousarray(np.asarray(arrival_s, dtype=np.float64))
+    n = len(w)
+    admit, done = np.empty(n), np.empty(n)
+    held = C.c_size_t()
+    p = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    _check(lib().gf_server_simulate(mem_budget, tile_rays, max_tiles, n, p(w), p(h), p(s), p(m), p(arr),
+                                    float(work_per_s), p(admit), p(done), C.byref(held)))
+    return admit, done, held.value

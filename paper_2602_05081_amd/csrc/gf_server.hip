@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "gf_internal.hpp"
+#include "gf_sched.hpp"
 
 gf_status gf_camera_launch(const gf_camera* cam, float* rays, hipStream_t sm);
 gf_status gf_check_camera(const gf_camera* cam, const char* who);
@@ -34,16 +35,11 @@ size_t gf_serve_workspace_bytes(int max_tiles, int tile_rays);
 
 namespace {
 
-const size_t kAlign = 256;
+using gfs::kAlign;
 const int kSlots = 2;  // batches in flight
 
-struct Req {
-    uint64_t id;
+struct Req : gfs::SchedReq {
     gf_request q;
-    int n;
-    size_t bytes, off;
-    int next_ray;   // first ray not yet put in a batch
-    int rays_done;  // rays whose batch completed
 };
 
 struct Batch {
@@ -52,19 +48,14 @@ struct Batch {
     std::vector<std::pair<uint64_t, int>> work;  // (request id, rays)
 };
 
-struct FreeBlock {
-    size_t off, size;
-};
-
 }  // namespace
 
 struct gf_server_s {
-    size_t budget, held;
+    gfs::Pool mem;  // offsets into `pool`
     int tile_rays, max_tiles;
     hipStream_t stream;
     char* pool;
     float* ws;  // tracking workspace of one batch (batches run in stream order)
-    std::vector<FreeBlock> freel;  // sorted by offset, coalesced
     std::deque<Req*> queue;
     std::vector<Req*> active;
     std::map<uint64_t, Req*> byid;
@@ -79,42 +70,6 @@ struct gf_server_s {
     uint64_t next_id;
 };
 
-static bool pool_alloc(gf_server_s* S, size_t bytes, size_t* off) {
-    for (size_t i = 0; i < S->freel.size(); ++i) {
-        FreeBlock& b = S->freel[i];
-        if (b.size >= bytes) {
-            *off = b.off;
-            b.off += bytes;
-            b.size -= bytes;
-            if (b.size == 0) S->freel.erase(S->freel.begin() + i);
-            S->held += bytes;
-            return true;
-        }
-    }
-    return false;
-}
-
-static void pool_free(gf_server_s* S, size_t off, size_t bytes) {
-    auto it = std::lower_bound(S->freel.begin(), S->freel.end(), off,
-                               [](const FreeBlock& b, size_t o) { return b.off < o; });
-    it = S->freel.insert(it, FreeBlock{off, bytes});
-    size_t i = it - S->freel.begin();
-    if (i + 1 < S->freel.size() && S->freel[i].off + S->freel[i].size == S->freel[i + 1].off) {
-        S->freel[i].size += S->freel[i + 1].size;
-        S->freel.erase(S->freel.begin() + i + 1);
-    }
-    if (i > 0 && S->freel[i - 1].off + S->freel[i - 1].size == S->freel[i].off) {
-        S->freel[i - 1].size += S->freel[i].size;
-        S->freel.erase(S->freel.begin() + i);
-    }
-    S->held -= bytes;
-}
-
-static size_t req_bytes(const gf_request* q) {
-    size_t b = (size_t)q->camera.width * q->camera.height * 8 * sizeof(float);
-    return (b + kAlign - 1) / kAlign * kAlign;
-}
-
 extern "C" gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_tiles, void* stream,
                                       gf_server* out) {
     if (!out) return gf_fail(GF_EINVAL, "gf_server_create: out is NULL");
@@ -122,8 +77,7 @@ extern "C" gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_
     if (mem_budget < kAlign || tile_rays < 64 || tile_rays > (1 << 20) || max_tiles < 1 || max_tiles > 65536)
         return gf_fail(GF_EINVAL, "gf_server_create: budget >= 256 B, 64 <= tile_rays <= 2^20, 1 <= max_tiles <= 65536");
     gf_server_s* S = new gf_server_s();
-    S->budget = mem_budget / kAlign * kAlign;
-    S->held = 0;
+    S->mem.reset(mem_budget / kAlign * kAlign);
     S->tile_rays = tile_rays;
     S->max_tiles = max_tiles;
     S->stream = (hipStream_t)stream;
@@ -139,9 +93,8 @@ extern "C" gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_
         gf_server_destroy(S);
         return gf_hip_check(e, what);
     };
-    hipError_t e = hipMalloc((void**)&S->pool, S->budget);
+    hipError_t e = hipMalloc((void**)&S->pool, S->mem.budget);
     if (e != hipSuccess) return fail(e, "hipMalloc(pool)");
-    S->freel.push_back(FreeBlock{0, S->budget});
     e = hipMalloc((void**)&S->ws, gf_serve_workspace_bytes(max_tiles, tile_rays));
     if (e != hipSuccess) return fail(e, "hipMalloc(workspace)");
     for (int k = 0; k < kSlots; ++k) {
@@ -184,13 +137,15 @@ extern "C" gf_status gf_server_submit(gf_server S, const gf_request* q, uint64_t
     if (st == GF_OK) st = gf_check_render_desc(&q->render, "gf_server_submit");
     if (st != GF_OK) return st;
     if (q->scene->depth > 64) return gf_fail(GF_EINVAL, "gf_server_submit: scene LBVH deeper than 64");
-    size_t bytes = req_bytes(q);
-    if (bytes > S->budget) return gf_fail(GF_EINVAL, "gf_server_submit: request needs %zu bytes, budget %zu", bytes,
-                                          S->budget);
+    size_t bytes = gfs::request_bytes(q->camera.width, q->camera.height);
+    if (bytes > S->mem.budget)
+        return gf_fail(GF_EINVAL, "gf_server_submit: request needs %zu bytes, budget %zu", bytes, S->mem.budget);
     Req* r = new Req();
     r->id = S->next_id++;
     r->q = *q;
     r->n = q->camera.width * q->camera.height;
+    r->spp = q->render.spp;
+    r->multiple = q->render.multiple != 0;
     r->bytes = bytes;
     r->off = 0;
     r->next_ray = 0;
@@ -211,7 +166,7 @@ static gf_status retire(gf_server_s* S, bool wait) {
             Req* r = S->byid[w.first];
             r->rays_done += w.second;
             if (r->rays_done == r->n) {
-                pool_free(S, r->off, r->bytes);
+                S->mem.release(r->off, r->bytes);
                 S->active.erase(std::find(S->active.begin(), S->active.end(), r));
                 S->done.push_back(r->id);
                 S->byid.erase(r->id);
@@ -229,7 +184,7 @@ static gf_status admit(gf_server_s* S) {
     while (!S->queue.empty()) {
         Req* r = S->queue.front();
         size_t off;
-        if (!pool_alloc(S, r->bytes, &off)) break;
+        if (!S->mem.alloc(r->bytes, &off)) break;
         r->off = off;
         gf_status st = gf_camera_launch(&r->q.camera, (float*)(S->pool + off), S->stream);
         if (st != GF_OK) return st;
@@ -244,17 +199,9 @@ static gf_status launch_batch(gf_server_s* S) {
     for (int k = 0; k < kSlots; ++k)
         if (!S->slot_busy[k]) slot = k;
     if (slot < 0) return GF_OK;
-    std::vector<Req*> open;
-    for (Req* r : S->active)
-        if (r->next_ray < r->n) open.push_back(r);
-    if (open.empty()) return GF_OK;
-    // shortest remaining work first (rays left x samples, multiple scattering
-    // weighted 3x), arrival order among equals: a small request that arrives
-    // behind a large one finishes in the next batch instead of after it
-    auto work = [](const Req* r) {
-        return (double)(r->n - r->next_ray) * r->q.render.spp * (r->q.render.multiple ? 3.0 : 1.0);
-    };
-    std::stable_sort(open.begin(), open.end(), [&](const Req* a, const Req* b) { return work(a) < work(b); });
+    std::vector<gfs::SchedReq*> act(S->active.begin(), S->active.end());
+    std::vector<gfs::TileRef> plan = gfs::plan_batch(act, S->tile_rays, S->max_tiles);
+    if (plan.empty()) return GF_OK;
     char* hreq = S->hreq[slot];
     char* htile = S->htile[slot];
     std::map<uint64_t, int> local;
@@ -263,24 +210,21 @@ static gf_status launch_batch(gf_server_s* S) {
     b.ev = S->events[slot];
     int ntiles = 0, nreq = 0;
     std::map<uint64_t, int> rays_in;
-    for (Req* r : open) {
-        while (ntiles < S->max_tiles && r->next_ray < r->n) {
-            auto it = local.find(r->id);
-            int li;
-            if (it == local.end()) {
-                li = nreq++;
-                local[r->id] = li;
-                gf_serve_fill_req(&r->q, (const float*)(S->pool + r->off), hreq + li * gf_serve_req_size());
-            } else {
-                li = it->second;
-            }
-            int cnt = std::min(S->tile_rays, r->n - r->next_ray);
-            int tile[4] = {li, r->next_ray, cnt, 0};
-            memcpy(htile + ntiles * gf_serve_tile_size(), tile, sizeof(tile));
-            r->next_ray += cnt;
-            rays_in[r->id] += cnt;
-            ++ntiles;
+    for (const gfs::TileRef& t : plan) {
+        const Req* r = static_cast<const Req*>(t.r);
+        auto it = local.find(r->id);
+        int li;
+        if (it == local.end()) {
+            li = nreq++;
+            local[r->id] = li;
+            gf_serve_fill_req(&r->q, (const float*)(S->pool + r->off), hreq + li * gf_serve_req_size());
+        } else {
+            li = it->second;
         }
+        int tile[4] = {li, t.first, t.count, 0};
+        memcpy(htile + ntiles * gf_serve_tile_size(), tile, sizeof(tile));
+        rays_in[r->id] += t.count;
+        ++ntiles;
     }
     for (auto& kv : rays_in) b.work.push_back(kv);
     GF_HIP(hipMemcpyAsync(S->dreq[slot], hreq, gf_serve_req_size() * nreq, hipMemcpyHostToDevice, S->stream));
@@ -324,6 +268,103 @@ extern "C" gf_status gf_server_stats(gf_server S, int* queued, int* in_flight, s
     if (!S) return gf_fail(GF_EINVAL, "gf_server_stats: NULL server");
     if (queued) *queued = (int)S->queue.size();
     if (in_flight) *in_flight = (int)S->active.size();
-    if (bytes_held) *bytes_held = S->held;
+    if (bytes_held) *bytes_held = S->mem.held;
+    return GF_OK;
+}
+
+// The executor's policy on a virtual clock, with no device work: requests
+// arrive at arrival_s[i]; each step retires the batches whose end has
+// passed, admits queued requests in arrival order while their rays fit the
+// pool, and launches a batch while fewer than two are in flight.  A batch
+// runs after the previous one ends and takes sum(rays x spp x (3 if
+// multiple)) / work_per_s seconds.
+extern "C" gf_status gf_server_simulate(size_t mem_budget, int tile_rays, int max_tiles, int64_t n,
+                                        const int32_t* width, const int32_t* height, const int32_t* spp,
+                                        const int32_t* multiple, const double* arrival_s, double work_per_s,
+                                        double* admit_s, double* done_s, size_t* max_held) {
+    if (n < 0 || (n > 0 && (!width || !height || !spp || !multiple || !arrival_s || !admit_s || !done_s)))
+        return gf_fail(GF_EINVAL, "gf_server_simulate: NULL argument");
+    if (mem_budget < kAlign || tile_rays < 64 || tile_rays > (1 << 20) || max_tiles < 1 || max_tiles > 65536 ||
+        !(work_per_s > 0.0))
+        return gf_fail(GF_EINVAL, "gf_server_simulate: budget >= 256 B, 64 <= tile_rays <= 2^20, "
+                                  "1 <= max_tiles <= 65536, work_per_s > 0");
+    gfs::Pool mem;
+    mem.reset(mem_budget / kAlign * kAlign);
+    std::vector<gfs::SchedReq> reqs((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        if (width[i] < 1 || height[i] < 1 || spp[i] < 1 || (int64_t)width[i] * height[i] > (1 << 28))
+            return gf_fail(GF_EINVAL, "gf_server_simulate: request %lld has an invalid size", (long long)i);
+        if (i > 0 && arrival_s[i] < arrival_s[i - 1])
+            return gf_fail(GF_EINVAL, "gf_server_simulate: arrivals must be sorted");
+        gfs::SchedReq& r = reqs[(size_t)i];
+        r.id = (uint64_t)i;
+        r.n = width[i] * height[i];
+        r.spp = spp[i];
+        r.multiple = multiple[i] != 0;
+        r.bytes = gfs::request_bytes(width[i], height[i]);
+        r.off = 0;
+        r.next_ray = r.rays_done = 0;
+        if (r.bytes > mem.budget)
+            return gf_fail(GF_EINVAL, "gf_server_simulate: request %lld needs %zu bytes, budget %zu", (long long)i,
+                           r.bytes, mem.budget);
+        admit_s[i] = done_s[i] = -1.0;
+    }
+    struct VBatch {
+        double end;
+        std::vector<std::pair<gfs::SchedReq*, int>> work;
+    };
+    std::deque<gfs::SchedReq*> queue;
+    std::vector<gfs::SchedReq*> active;
+    std::deque<VBatch> inflight;
+    double now = 0.0, last_end = 0.0;
+    int64_t next = 0, finished = 0;
+    size_t peak = 0;
+    while (finished < n) {
+        while (next < n && arrival_s[next] <= now) queue.push_back(&reqs[(size_t)next++]);
+        while (!inflight.empty() && inflight.front().end <= now) {
+            for (auto& w : inflight.front().work) {
+                gfs::SchedReq* r = w.first;
+                r->rays_done += w.second;
+                if (r->rays_done == r->n) {
+                    mem.release(r->off, r->bytes);
+                    active.erase(std::find(active.begin(), active.end(), r));
+                    done_s[r->id] = inflight.front().end;
+                    ++finished;
+                }
+            }
+            inflight.pop_front();
+        }
+        while (!queue.empty()) {
+            size_t off;
+            if (!mem.alloc(queue.front()->bytes, &off)) break;
+            queue.front()->off = off;
+            admit_s[queue.front()->id] = now;
+            active.push_back(queue.front());
+            queue.pop_front();
+        }
+        peak = std::max(peak, mem.held);
+        while ((int)inflight.size() < kSlots) {
+            std::vector<gfs::TileRef> plan = gfs::plan_batch(active, tile_rays, max_tiles);
+            if (plan.empty()) break;
+            VBatch b;
+            double work = 0.0;
+            std::map<gfs::SchedReq*, int> rays_in;
+            for (const gfs::TileRef& t : plan) {
+                work += (double)t.count * t.r->spp * (t.r->multiple ? 3.0 : 1.0);
+                rays_in[t.r] += t.count;
+            }
+            for (auto& kv : rays_in) b.work.push_back(kv);
+            b.end = std::max(now, last_end) + work / work_per_s;
+            last_end = b.end;
+            inflight.push_back(b);
+        }
+        if (finished == n) break;
+        double t_next = INFINITY;
+        if (next < n) t_next = arrival_s[next];
+        if (!inflight.empty()) t_next = std::min(t_next, inflight.front().end);
+        if (!(t_next < INFINITY)) return gf_fail(GF_ESTATE, "gf_server_simulate: no event left");
+        now = std::max(now, t_next);
+    }
+    if (max_held) *max_held = peak;
     return GF_OK;
 }
