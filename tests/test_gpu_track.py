@@ -248,3 +248,38 @@ def test_render_full_size_multiple_stochastic_blob1m():
     print("pooled %.2f worst %.2f over %d pixels" % (pooled, worst, ok.sum()), flush=True)
     assert pooled < 3.0 and worst < 5.0
     assert np.all(np.abs(Tm[~ok] - exact[~ok]) < 2e-3)
+
+
+def test_render_edge_cases():
+    """Rays that miss the scene or have an empty window escape with weight 1
+    (L = L_env, T = 1, zero variance); an empty mask lets every ray escape;
+    a one-ray launch and a ragged 7-ray launch give the same bits for the
+    same ray."""
+    gf = require_gpu()
+    params, rho = W.scene("tiny256"), W.rho("tiny256")
+    scene = gf.Scene(dev(params), rho=rho)
+    rays = np.zeros((7, 8), np.float32)
+    rays[0:3, 0:3] = [[3.0, 3.0, 3.0], [-2.0, 0.5, 0.5], [0.5, 0.5, 5.0]]  # outside, pointing away
+    rays[0:3, 3:6] = [[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0], [0.0, 0.0, 1.0]]
+    rays[0:3, 7] = np.inf
+    rays[3:5, 0:3] = [[0.5, 0.5, 0.5], [0.3, 0.6, 0.4]]  # inside, empty window
+    rays[3:5, 3:6] = [[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]]
+    rays[3:5, 6] = rays[3:5, 7] = 0.25
+    rays[5:7, 0:3] = [[0.5, 0.5, -1.0], [0.2, 0.7, -1.0]]  # through the volume
+    rays[5:7, 5] = 1.0
+    rays[5:7, 7] = np.inf
+    for multiple in (False, True):
+        d = gf.render_desc(spp=4, multiple=multiple, albedo=0.9, hg_g=0.3, seed=13)
+        L, Lv, T, Tv = (host(x) for x in gf.gf_render(scene, dev(rays), d))
+        assert np.all(L[:5] == 1.0) and np.all(T[:5] == 1.0)
+        assert np.all(Lv[:5] == 0.0) and np.all(Tv[:5] == 0.0)
+        assert np.all(np.isfinite(L)) and np.all(np.isfinite(T))
+        L1, _, T1, _ = (host(x) for x in gf.gf_render(scene, dev(rays[6:7]), d))
+        # the ray's streams are keyed by its index: index 6 in the ragged
+        # launch is index 0 alone, so compare the launch with itself shifted
+        shifted = np.concatenate([rays[6:7], rays[:6]])
+        L2, _, T2, _ = (host(x) for x in gf.gf_render(scene, dev(shifted), d))
+        assert L1[0] == L2[0] and T1[0] == T2[0]
+        d0 = gf.render_desc(spp=4, multiple=multiple, albedo=0.9, hg_g=0.3, seed=13, mask=gf.make_mask(0))
+        L0, _, T0, _ = (host(x) for x in gf.gf_render(scene, dev(rays), d0))
+        assert np.all(L0 == 1.0) and np.all(T0 == 1.0)
