@@ -36,6 +36,7 @@
 #define TS_LDS 24    // per-lane stack entries kept in LDS; deeper ones go to the workspace
 #define TK 64        // tentative points per window
 #define CQ 8         // leaf candidates a lane queues before the wave processes them
+#define DRAIN_LANES 4  // the wave drains its leaf queues once fewer lanes than this can step
 #define SG 8         // samples whose secondary paths a lane follows back to back
 // Largest weight of a stochastic cell (3 / p_k with p_k >= 1/6): the
 // majorant's multiplier of the drawn cell never needs to exceed it, so the
@@ -301,11 +302,15 @@ static __device__ __forceinline__ void lane_traverse(const SceneView& S, uint32_
     int sp = 0, node = 0, cnt = 0;
     bool trav = true;
     // one wave-uniform loop: a node step for every lane that still
-    // traverses and has room in its queue; when no lane can step, the
-    // queues are drained
+    // traverses and has room in its queue; the queues are drained when fewer
+    // than DRAIN_LANES lanes can step and some queue holds work (or when no
+    // lane can step), so a few long traversals do not keep the rest of the
+    // wave waiting on full queues.  A lane's leaves keep their order, so the
+    // drain points do not change its result.
     for (;;) {
         bool step = trav && cnt <= CQ - 2;
-        if (!__any(step)) {
+        const unsigned long long bs = __ballot(step);
+        if (bs == 0ull || (__popcll(bs) < DRAIN_LANES && __any(cnt > 0))) {
             for (int k = 0; k < cnt; ++k) leaves(lm.cand[k * TR_THREADS]);
             cnt = 0;
             if (!__any(trav)) break;
