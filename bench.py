@@ -241,7 +241,7 @@ def serving(args, gf, W, np, torch):
         return lambda k, t: log("serving (%s): request %d done at %.1f s" % (tag, k, t))
 
     lat_s, mk_s, _, held = serve.run_server(scenes, reqs, arrivals, mem_budget=1 << 30, tile_rays=4096,
-                                            max_tiles=96, time_limit=600, on_done=done("batching"))
+                                            max_tiles=192, time_limit=600, on_done=done("batching"))
     log("serving: continuous batching done in %.1f s" % mk_s)
     lat_p, mk_p, _ = serve.run_plain(scenes, reqs, arrivals, time_limit=600, on_done=done("plain"))
     log("serving: plain renderer done in %.1f s" % mk_p)
