@@ -206,13 +206,13 @@ def measured_traffic(workload, kernel):
     summary (profiles/<kernel>_<workload>_pmc.txt), scaled by the calibration
     factors recorded there; None when no summary exists or the HIP sources
     changed since it was taken."""
-    sys.path.insert(0, os.path.join(ROOT, "profiles"))
-    import summarize
+    sys.path.insert(0, ROOT)
+    import profile_summary
     path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, workload))
     if not os.path.exists(path):
         return None
     text = open(path).read().splitlines()
-    if not any(l.startswith("# source hash: %s" % summarize.source_hash()) for l in text):
+    if not any(l.startswith("# source hash: %s" % profile_summary.source_hash()) for l in text):
         return None
     name = {"optical_depth": "void k_tau<false>", "render": "void k_render<false>"}[kernel]
     for line in text:

@@ -1,9 +1,9 @@
-"""Summarises rocprofv3 CSV output into the short text files kept in this folder.
+"""Summarises rocprofv3 CSV output into the short text files kept in profiles/.
 
-    python profiles/summarize.py stats <kernel_stats.csv> <out.txt> "<command>"
-    python profiles/summarize.py pmc <fetch_counter_collection.csv> <write_counter_collection.csv> <out.txt> \
+    python profile_summary.py stats <kernel_stats.csv> <out.txt> "<command>"
+    python profile_summary.py pmc <fetch_counter_collection.csv> <write_counter_collection.csv> <out.txt> \
         "<fetch command>" "<write command>" <calibration bytes>
-    python profiles/summarize.py counters <counter_collection.csv> <out.txt> "<command>"
+    python profile_summary.py counters <counter_collection.csv> <out.txt> "<command>"
 
 `stats` keeps each kernel's call count, total and average duration.
 `counters` keeps, per kernel, the average per dispatch of every counter of
@@ -26,7 +26,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 def source_hash():
     """sha256 over the HIP sources; bench.py trusts a counter summary only while it matches"""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(HERE, "..", "paper_2602_05081_amd", "csrc", "*"))):
+    for f in sorted(glob.glob(os.path.join(HERE, "paper_2602_05081_amd", "csrc", "*"))):
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
