@@ -730,6 +730,19 @@ static __device__ __forceinline__ int ray_of_tr(int gid, int n, int tile_w) {
     return py < height ? py * tile_w + px : -1;
 }
 
+// Order in which a launch hands out the chunks of an image: rows of 8x8
+// tiles from the middle of the image outward (middle row, the one above, the
+// one below, ...), so the dense centre, whose chunks take longest, starts
+// first and the launch does not end on a few slow chunks.  A bijection on
+// the chunk indices; a ray's result does not depend on when it is traced.
+static __device__ __forceinline__ int tile_order(int c, int nchunks, int tile_w) {
+    if (tile_w <= 0) return c;
+    const int tiles_x = tile_w >> 3, tiles_y = nchunks / tiles_x;
+    const int q = c / tiles_x, tx = c - q * tiles_x, mid = tiles_y >> 1;
+    const int ty = (q & 1) ? mid - ((q + 1) >> 1) : mid + (q >> 1);
+    return ty * tiles_x + tx;
+}
+
 static int64_t tr_threads(int64_t n, int tile_w) {
     if (tile_w <= 0) return n;
     return (int64_t)(tile_w / 8) * ((n / tile_w + 7) / 8) * 64;
@@ -984,7 +997,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, c
     __shared__ int pstk[TR_STACK];
     Work wk{};
     for (int c = next_chunk((unsigned*)ws); c < nchunks; c = next_chunk((unsigned*)ws)) {
-        int idx = ray_of_tr(c * TR_THREADS + (int)threadIdx.x, n, tile_w);
+        int idx = ray_of_tr(tile_order(c, nchunks, tile_w) * TR_THREADS + (int)threadIdx.x, n, tile_w);
         float o[2];
         ratio_rays<false>(S, M, rays, idx, spp, seed, lm, pstk, wk, o);
         if (idx >= 0) {
@@ -1004,7 +1017,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, 
     __shared__ int pstk[TR_STACK];
     Work wk{};
     for (int c = next_chunk((unsigned*)ws); c < nchunks; c = next_chunk((unsigned*)ws)) {
-        int idx = ray_of_tr(c * TR_THREADS + (int)threadIdx.x, n, tile_w);
+        int idx = ray_of_tr(tile_order(c, nchunks, tile_w) * TR_THREADS + (int)threadIdx.x, n, tile_w);
         float o[4];
         render_rays<COUNT>(S, M, A, rays, idx, lm, pstk, wk, o);
         if (!COUNT && idx >= 0) {
