@@ -20,9 +20,12 @@ quantity drawn in float64, then cast to float32 at the end):
 
     [blob field parameters]  mu  q  s  f-direction  f-magnitude  phi  alpha
 
-after which, in blob scenes only, every fourth primitive (index % 4 == 0) is
-turned into a Gaussian of the low-pass level: f = 0, phi = 0, alpha scaled by 4.
-Uniform scenes are Gabor kernels only (a zero-mean signed field).
+By default every primitive is a Gabor kernel (a signed field).  With
+``base_level=True`` (blob scenes) every fourth primitive (index % 4 == 0) is
+then turned into a Gaussian of the low-pass level: f = 0, phi = 0, alpha
+scaled by 4 -- a positive base under the Gabor residuals, shaped like the
+paper's assets (Sec. 4.3: Gaussians for the low-pass, Gabor kernels for the
+remaining bands).
 """
 from __future__ import annotations
 
@@ -77,14 +80,16 @@ def uniform_scene(n: int = 256, seed: int = 0, smin: float = 0.02, smax: float =
     return _common_tail(g, mu, smin, smax)
 
 
-def blob_scene(n: int, seed: int, smin: float = 0.003, smax: float = 0.05, n_blobs: int = 64) -> np.ndarray:
+def blob_scene(n: int, seed: int, smin: float = 0.003, smax: float = 0.05, n_blobs: int = 64,
+               base_level: bool = False) -> np.ndarray:
     """Means drawn from a sum of ``n_blobs`` isotropic Gaussian blobs.
 
     Blob centres are uniform in [0.15, 0.85]^3, blob radii log-uniform in
     [0.03, 0.15], blob weights uniform in [0.5, 1.5].  A mean is drawn by picking
     a blob with probability proportional to its weight and adding an isotropic
     normal offset of the blob's radius; means outside the unit cube are redrawn.
-    Every fourth primitive belongs to the Gaussian low-pass level.
+    With ``base_level`` every fourth primitive belongs to a Gaussian low-pass
+    level (off by default: Gabor kernels only).
     """
     g = _rng(seed)
     centres = g.uniform(0.15, 0.85, size=(n_blobs, 3))
@@ -99,7 +104,7 @@ def blob_scene(n: int, seed: int, smin: float = 0.003, smax: float = 0.05, n_blo
         ok = np.all((cand >= 0.0) & (cand <= 1.0), axis=1)
         mu[todo[ok]] = cand[ok]
         todo = todo[~ok]
-    return _common_tail(g, mu, smin, smax, base_level=True)
+    return _common_tail(g, mu, smin, smax, base_level=base_level)
 
 
 def jitter_scene(params: np.ndarray, seed: int, rel: float = 0.05) -> np.ndarray:

@@ -25,6 +25,10 @@ WORKLOADS = {
     "blob100k": dict(kind="blob", n=100_000, seed=1, camera=("pinhole", 512, 512)),
     # 1M Gabors, same generator; 1024^2 pinhole
     "blob1m": dict(kind="blob", n=1_000_000, seed=2, camera=("pinhole", 1024, 1024)),
+    # the same scenes with a Gaussian low-pass level (every fourth primitive
+    # f = 0, phi = 0, alpha x 4): a mostly positive field like the paper's assets
+    "blob100k_lp": dict(kind="blob", n=100_000, seed=1, camera=("pinhole", 512, 512), base_level=True),
+    "blob1m_lp": dict(kind="blob", n=1_000_000, seed=2, camera=("pinhole", 1024, 1024), base_level=True),
     # 50k Gabors, eight 256^2 views; the target scene is a 5% jitter (seed 4)
     "diff50k": dict(kind="blob", n=50_000, seed=3, camera=("eight", 256, 256), jitter_seed=4),
     # resident serving scenes
@@ -37,11 +41,22 @@ WORKLOADS = {
 SERVE_SCENES = ["serve10k", "serve100k", "serve500k", "serve2m"]
 
 
+def describe(name: str) -> str:
+    """One-line description of a workload's scene (for benchmark records)."""
+    w = WORKLOADS[name]
+    if w["kind"] == "uniform":
+        return "%d Gabors, uniform means, scales logU[%g, %g], seed %d" % (w["n"], w["smin"], w["smax"], w["seed"])
+    lp = w.get("base_level", False)
+    return "%d %s, 64-blob field, scales logU[0.003, 0.05], seed %d" % (
+        w["n"], "primitives (every 4th a Gaussian of the low-pass level, alpha x4)" if lp else "Gabors (Gabor-only)",
+        w["seed"])
+
+
 def scene(name: str) -> np.ndarray:
     w = WORKLOADS[name]
     if w["kind"] == "uniform":
         return scenes.uniform_scene(w["n"], w["seed"], w["smin"], w["smax"])
-    return scenes.blob_scene(w["n"], w["seed"])
+    return scenes.blob_scene(w["n"], w["seed"], base_level=w.get("base_level", False))
 
 
 def target_scene(name: str) -> np.ndarray:

@@ -18,11 +18,17 @@
  *   - the frequency-level / orientation-bin partition and visibility masks
  *     (Sec. 4.5 implementation details: V_l = 2^l, ray mask AND);
  *   - a Morton-ordered Karras linear BVH over the truncated ellipsoids;
- *   - ratio tracking and weighted delta tracking with local majorants, and the
- *     single / multiple scattering estimators built on them;
+ *   - ratio tracking and weighted delta tracking with local majorants, free
+ *     flights by inversion of the cumulative optical depth with a bisection
+ *     solver (Sec. 3 CDF inversion; Sec. 4.4 distance sampling), and the
+ *     single / multiple scattering estimators built on them, with shadow rays
+ *     optionally restricted to chosen cells (Zero-NEE, Sec. 4.5 implementation
+ *     details);
  *   - the per-segment stochastic band / orientation masks (Sec. 4.5.1-4.5.2,
- *     Appendix B tables: uniform + control variate over levels, importance
- *     sampling over orientation bins with w = exp(-f0^2 a^2 / 2));
+ *     Appendix B tables): every frequency-level strategy and every
+ *     orientation-bin strategy of the two tables;
+ *   - the continuous LOD cutoff of camera rays (supplementary, LOD selection)
+ *     and adaptive clamping of the support (Sec. 4.4, in a conservative form);
  *   - analytic gradients of optical depth with respect to all 15 parameters.
  *
  * Parameter record (15 doubles per primitive, the float32 inputs promoted):
@@ -34,7 +40,8 @@
  *   - whitening W = S^-1 R^T (so W^T W = Sigma^-1); whitened frequency is the
  *     covector k_W = S R^T omega, so that k_W . W y = omega . y;
  *   - the kernel carries a phase: cos(omega^T (x - mu) + phi);
- *   - support is {M(x) < r^2}, M the squared Mahalanobis distance, r = 3;
+ *   - support is {M(x) < r^2}, M the squared Mahalanobis distance, r = 3
+ *     (or the primitive's clamped radius, see clamp_radius);
  *   - the density is signed; a scene scale rho multiplies every weight.
  *
  * Parity status: every function below is pinned by a CPU test (closed forms,
@@ -135,6 +142,8 @@ typedef struct {
     double mu[3], qh[4], qn, R[3][3], s[3], f[3], om[3], phi, alpha;
     double A[3][3]; /* Sigma^-1 = R S^-2 R^T */
     double c;       /* (2 pi)^-3/2 / (s0 s1 s2) */
+    double rr;      /* truncation radius of this primitive (Mahalanobis units) */
+    double f2;      /* |f|^2 in (cycles / unit)^2, order (fx^2 + fy^2) + fz^2 */
 } prim_t;
 
 /* Hamilton rotation of the unit quaternion (w, x, y, z), local -> world. */
@@ -152,8 +161,36 @@ static void quat_to_R(const double q[4], double R[3][3])
     R[2][2] = 1.0 - 2.0 * (x * x + y * y);
 }
 
-static void prim_decode(const double* p, prim_t* P)
+/* Adaptive clamping (Sec. 4.4, adaptive clamping), in a conservative form.
+ * For a unit-speed ray at whitened distance h from the centre, the part of
+ * rho alpha int g dt lying outside Mahalanobis radius E is at most
+ *   rho |alpha| c sqrt(2 pi) / |W v| exp(-E^2 / 2)
+ *   <= rho |alpha| s_max / (2 pi s0 s1 s2) exp(-E^2 / 2)
+ * (Gaussian tail bound erfc(x) <= exp(-x^2), and |W v| >= 1 / s_max).  Setting
+ * this to eps gives E^2 = 2 ln(rho |alpha| s_max / (2 pi s0 s1 s2 eps)); the
+ * primitive's radius becomes min(r, E) (0 when E^2 <= 0: the whole kernel is
+ * below eps on every ray).  The paper's extent drops alpha and the Jacobian
+ * and subtracts k_W^2, which no ray perpendicular to k_W attains, so it is not
+ * a bound; the carrier term is left out here for that reason.
+ * eps = 0 (default) keeps radius r for every primitive. */
+static double g_clamp_eps = 0.0;
+
+void or_set_clamp_eps(double eps) { g_clamp_eps = eps; }
+
+static double clamp_radius(const double* p, double r, double rho)
 {
+    if (!(g_clamp_eps > 0.0)) return r;
+    double smax = fmax(p[7], fmax(p[8], p[9]));
+    double arg = rho * fabs(p[14]) * smax / (2.0 * OR_PI * p[7] * p[8] * p[9] * g_clamp_eps);
+    if (!(arg > 1.0)) return 0.0;
+    double E = sqrt(2.0 * log(arg));
+    return E < r ? E : r;
+}
+
+static void prim_decode(const double* p, prim_t* P, double r, double rho)
+{
+    P->rr = clamp_radius(p, r, rho);
+    P->f2 = (p[10] * p[10] + p[11] * p[11]) + p[12] * p[12];
     for (int a = 0; a < 3; ++a) P->mu[a] = p[a];
     double qn = sqrt(((p[3] * p[3] + p[4] * p[4]) + p[5] * p[5]) + p[6] * p[6]);
     P->qn = qn;
@@ -176,8 +213,9 @@ static void prim_decode(const double* p, prim_t* P)
 }
 
 /* kernel value g(x) (no alpha), truncated at M < r^2 */
-static double kernel_at(const prim_t* P, const double x[3], double r, double* Mout)
+static double kernel_at(const prim_t* P, const double x[3], double* Mout)
 {
+    const double r = P->rr;
     double y[3] = {x[0] - P->mu[0], x[1] - P->mu[1], x[2] - P->mu[2]};
     double M = 0.0;
     for (int a = 0; a < 3; ++a)
@@ -200,8 +238,9 @@ typedef struct {
 /* Chord of the ray with the truncated ellipsoid M < r^2, clipped to [tmin, tmax].
  * Whitened arc length u = n (t - tc), n = ||W v||, tc the Mahalanobis-closest
  * point; M(t) = h^2 + u^2 and the carrier phase is theta + Omega u. */
-static int hit_geom(const prim_t* P, const double* ray, double r, hit_t* H)
+static int hit_geom(const prim_t* P, const double* ray, hit_t* H)
 {
+    const double r = P->rr;
     const double* o = ray;
     const double* v = ray + 3;
     double d[3] = {o[0] - P->mu[0], o[1] - P->mu[1], o[2] - P->mu[2]};
@@ -265,9 +304,9 @@ void or_segment_integral(const double* prim, const double* ray, double r, double
 {
     prim_t P;
     hit_t H;
-    prim_decode(prim, &P);
+    prim_decode(prim, &P, r, 1.0);
     memset(out, 0, 8 * sizeof(double));
-    if (!hit_geom(&P, ray, r, &H)) return;
+    if (!hit_geom(&P, ray, &H)) return;
     out[0] = seg_integral(&P, &H);
     out[1] = 1.0;
     out[2] = H.h2;
@@ -323,7 +362,7 @@ void or_cell_medians(const double* params, int64_t n, double* med12)
         for (int64_t i = 0; i < n; ++i) {
             if (cell[i] != c) continue;
             prim_t P;
-            prim_decode(params + 15 * i, &P);
+            prim_decode(params + 15 * i, &P, 3.0, 1.0);
             double kw2 = 0.0;
             for (int k = 0; k < 3; ++k) {
                 double rt = P.R[0][k] * P.om[0] + P.R[1][k] * P.om[1] + P.R[2][k] * P.om[2];
@@ -370,8 +409,9 @@ static double* mask_weights(const double* params, int64_t n, uint64_t cells, con
 }
 
 /* cheap conservative reject: distance from mu to the ray line exceeds r * s_max */
-static int sphere_reject(const prim_t* P, const double* ray, double r)
+static int sphere_reject(const prim_t* P, const double* ray)
 {
+    const double r = P->rr;
     const double* o = ray;
     const double* v = ray + 3;
     double d[3] = {o[0] - P->mu[0], o[1] - P->mu[1], o[2] - P->mu[2]};
@@ -382,16 +422,34 @@ static int sphere_reject(const prim_t* P, const double* ray, double r)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Continuous LOD (supplementary "LOD Selection"): a camera of vertical field  */
+/* of view phi and R pixels sees the width 2 d tan(phi/2) at distance d, whose  */
+/* Nyquist limit is pi R / (2 d tan(phi/2)) rad per unit, i.e.                */
+/* R / (4 d tan(phi/2)) cycles per unit.  With lod_k = R / (4 tan(phi/2)) a    */
+/* primitive is integrated along a camera ray only when |f| d <= lod_k, d the   */
+/* distance from the ray origin to the primitive's point of closest approach   */
+/* (Mahalanobis-closest point tc, d = tc |v|); primitives at or behind the      */
+/* origin (tc <= 0) are kept.  lod_k <= 0 turns the cutoff off.               */
+/* ------------------------------------------------------------------------- */
+static int lod_keep(const prim_t* P, const hit_t* H, const double* ray, double lod_k)
+{
+    if (!(lod_k > 0.0) || !(H->tc > 0.0)) return 1;
+    double v2 = ray[3] * ray[3] + ray[4] * ray[4] + ray[5] * ray[5];
+    return P->f2 * (H->tc * H->tc * v2) <= lod_k * lod_k;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Optical depth per ray: tau = rho sum_i alpha_i int g_i over the clipped    */
 /* chord (Sec. 3, Eq. 2), brute force over every primitive.  abs_sum =       */
 /* rho sum_i |alpha_i I_i|.  envelope != 0 integrates |alpha| times the       */
 /* Gaussian envelope only (omega = 0, phi = 0).                              */
 /* ------------------------------------------------------------------------- */
 void or_tau(const double* params, int64_t n, double rho, double r, const double* rays, int64_t nr,
-            uint64_t cells, const uint32_t* bits, int envelope, double* tau, double* abs_sum, int64_t* nhit)
+            uint64_t cells, const uint32_t* bits, int envelope, double lod_k, double* tau, double* abs_sum,
+            int64_t* nhit)
 {
     prim_t* P = (prim_t*)malloc(sizeof(prim_t) * (n ? n : 1));
-    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i]);
+    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i], r, rho);
     double* wt = mask_weights(params, n, cells, bits);
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t k = 0; k < nr; ++k) {
@@ -400,9 +458,10 @@ void or_tau(const double* params, int64_t n, double rho, double r, const double*
         int64_t cnt = 0;
         for (int64_t i = 0; i < n; ++i) {
             if (wt[i] == 0.0) continue;
-            if (sphere_reject(&P[i], ray, r)) continue;
+            if (sphere_reject(&P[i], ray)) continue;
             hit_t H;
-            if (!hit_geom(&P[i], ray, r, &H)) continue;
+            if (!hit_geom(&P[i], ray, &H)) continue;
+            if (!lod_keep(&P[i], &H, ray, lod_k)) continue;
             double Ii = envelope ? fabs(P[i].alpha) * seg_envelope(&P[i], &H) : P[i].alpha * seg_integral(&P[i], &H);
             acc += Ii;
             aacc += fabs(Ii);
@@ -421,13 +480,13 @@ void or_kappa(const double* params, int64_t n, double rho, double r, uint64_t ce
               const double* pts, int64_t np, double* kappa)
 {
     prim_t* P = (prim_t*)malloc(sizeof(prim_t) * (n ? n : 1));
-    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i]);
+    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i], r, rho);
     double* wt = mask_weights(params, n, cells, bits);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < np; ++k) {
         double acc = 0.0;
         for (int64_t i = 0; i < n; ++i)
-            if (wt[i] != 0.0) acc += P[i].alpha * kernel_at(&P[i], pts + 3 * k, r, NULL);
+            if (wt[i] != 0.0) acc += P[i].alpha * kernel_at(&P[i], pts + 3 * k, NULL);
         kappa[k] = rho * acc;
     }
     free(wt);
@@ -488,8 +547,9 @@ static float round_up_f(double x)
     return f;
 }
 
-/* Leaf half-extent along each world axis of the ellipsoid M < r^2. */
-static void leaf_extent(const double* p, double r, double e[3])
+/* Leaf half-extent along each world axis of the ellipsoid M < rr^2 (rr the
+ * primitive's truncation radius). */
+static void leaf_extent(const double* p, double rr, double e[3])
 {
     double qn = sqrt(((p[3] * p[3] + p[4] * p[4]) + p[5] * p[5]) + p[6] * p[6]);
     double q[4] = {p[3] / qn, p[4] / qn, p[5] / qn, p[6] / qn};
@@ -498,11 +558,11 @@ static void leaf_extent(const double* p, double r, double e[3])
     for (int a = 0; a < 3; ++a) {
         double t0 = R[a][0] * p[7], t1 = R[a][1] * p[8], t2 = R[a][2] * p[9];
         double sum = (t0 * t0 + t1 * t1) + t2 * t2;
-        e[a] = r * sqrt(sum);
+        e[a] = rr * sqrt(sum);
     }
 }
 
-int or_lbvh(const double* params, int64_t n, double r, uint64_t* keys, int32_t* perm, int32_t* left,
+int or_lbvh(const double* params, int64_t n, double rho, double r, uint64_t* keys, int32_t* perm, int32_t* left,
             int32_t* right, int32_t* parent, float* aabb, uint64_t* cellor)
 {
     if (n < 1) return -1;
@@ -565,7 +625,7 @@ int or_lbvh(const double* params, int64_t n, double r, uint64_t* keys, int32_t* 
     for (int64_t j = 0; j < n; ++j) {
         const double* p = params + 15 * (int64_t)perm[j];
         double e[3];
-        leaf_extent(p, r, e);
+        leaf_extent(p, clamp_radius(p, r, rho), e);
         float* bx = aabb + 6 * (L0 + j);
         for (int a = 0; a < 3; ++a) {
             bx[a] = round_down_f(p[a] - e[a]);
@@ -627,12 +687,12 @@ static int slab(const float* bx, const double* ray)
     return t0 <= t1;
 }
 
-void or_traverse_counts(const double* params, int64_t n, double r, const int32_t* perm, const int32_t* left,
+void or_traverse_counts(const double* params, int64_t n, double rho, double r, const int32_t* perm, const int32_t* left,
                         const int32_t* right, const float* aabb, const uint64_t* cellor, const double* rays,
                         int64_t nr, uint64_t cells, const uint32_t* bits, int64_t* nnode, int64_t* nhit)
 {
     prim_t* P = (prim_t*)malloc(sizeof(prim_t) * n);
-    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i]);
+    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i], r, rho);
     const int64_t L0 = n - 1;
 #pragma omp parallel for schedule(dynamic, 8)
     for (int64_t k = 0; k < nr; ++k) {
@@ -650,7 +710,7 @@ void or_traverse_counts(const double* params, int64_t n, double r, const int32_t
                 int64_t pi = perm[id - L0];
                 if (bits && !((bits[pi >> 5] >> (pi & 31)) & 1u)) continue;
                 hit_t H;
-                if (hit_geom(&P[pi], ray, r, &H)) ++ch;
+                if (hit_geom(&P[pi], ray, &H)) ++ch;
             } else {
                 stack[sp++] = left[id];
                 stack[sp++] = right[id];
@@ -717,9 +777,9 @@ static double rng_u(rng_t* g)
 
 /* ------------------------------------------------------------------------- */
 /* Local majorants along one ray: every primitive whose truncated chord meets */
-/* [t0, inf) contributes an interval; between consecutive interval ends the   */
-/* active set is fixed and                                                    */
-/*   kbar = rho sum_{i active} wt_i |alpha_i| c_i exp(-m_i / 2),              */
+/* [tmin, tmax] contributes an interval; between consecutive interval ends    */
+/* the active set is fixed and                                                */
+/*   kbar = rho sum_{i active} |wt_i alpha_i| c_i exp(-m_i / 2),              */
 /* m_i the minimum of M_i over the piece (closed form: clamp the closest      */
 /* point into the piece).  kbar >= |kappa| on the piece.                      */
 /* ------------------------------------------------------------------------- */
@@ -737,14 +797,18 @@ typedef struct {
 
 static int cmp_d(const void* a, const void* b) { return cmp_double(a, b); }
 
-static void collect_chords(const prim_t* P, const double* wt, int64_t n, double r, const double* ray, chords_t* C)
+/* chords of the primitives with a non-zero weight (and, with lod_k > 0, the
+ * continuous-LOD cutoff of camera rays) */
+static void collect_chords(const prim_t* P, const double* wt, int64_t n, const double* ray, double lod_k,
+                           chords_t* C)
 {
     C->nch = 0;
     for (int64_t i = 0; i < n; ++i) {
         if (wt[i] == 0.0) continue;
-        if (sphere_reject(&P[i], ray, r)) continue;
+        if (sphere_reject(&P[i], ray)) continue;
         hit_t H;
-        if (!hit_geom(&P[i], ray, r, &H)) continue;
+        if (!hit_geom(&P[i], ray, &H)) continue;
+        if (!lod_keep(&P[i], &H, ray, lod_k)) continue;
         if (C->nch == C->cap) {
             C->cap = C->cap ? 2 * C->cap : 64;
             C->ch = (chord_t*)realloc(C->ch, sizeof(chord_t) * C->cap);
@@ -776,30 +840,30 @@ static double piece_majorant(const prim_t* P, const double* wt, const chords_t* 
         double tcl = c->tc < a ? a : (c->tc > b ? b : c->tc);
         double du = c->n * (tcl - c->tc);
         double m = c->h2 + du * du;
-        acc += wt[c->i] * fabs(P[c->i].alpha) * P[c->i].c * exp(-0.5 * m);
+        acc += fabs(wt[c->i] * P[c->i].alpha) * P[c->i].c * exp(-0.5 * m);
     }
     return rho * acc;
 }
 
-static double piece_density(const prim_t* P, const double* wt, const chords_t* C, double rho, double r,
-                            const double* ray, double t)
+static double piece_density(const prim_t* P, const double* wt, const chords_t* C, double rho, const double* ray,
+                            double t)
 {
     double x[3] = {ray[0] + t * ray[3], ray[1] + t * ray[4], ray[2] + t * ray[5]};
     double acc = 0.0;
     for (int64_t k = 0; k < C->nch; ++k) {
         const chord_t* c = &C->ch[k];
         if (t < c->tin || t > c->tout) continue;
-        acc += wt[c->i] * P[c->i].alpha * kernel_at(&P[c->i], x, r, NULL);
+        acc += wt[c->i] * P[c->i].alpha * kernel_at(&P[c->i], x, NULL);
     }
     return rho * acc;
 }
 
 /* Ratio tracking transmittance over [ray.tmin, ray.tmax]:
  * T = prod_j (1 - kappa(x_j) / kbar_j) over a Poisson process of rate kbar. */
-static double ratio_track(const prim_t* P, const double* wt, int64_t n, double rho, double r, const double* ray,
+static double ratio_track(const prim_t* P, const double* wt, int64_t n, double rho, const double* ray, double lod_k,
                           rng_t* g, chords_t* C)
 {
-    collect_chords(P, wt, n, r, ray, C);
+    collect_chords(P, wt, n, ray, lod_k, C);
     double T = 1.0;
     for (int64_t e = 0; e + 1 < C->nev; ++e) {
         double a = C->ev[e], b = C->ev[e + 1];
@@ -810,7 +874,7 @@ static double ratio_track(const prim_t* P, const double* wt, int64_t n, double r
         for (;;) {
             t += -log(rng_u(g)) / kb;
             if (t >= b) break;
-            T *= 1.0 - piece_density(P, wt, C, rho, r, ray, t) / kb;
+            T *= 1.0 - piece_density(P, wt, C, rho, ray, t) / kb;
         }
     }
     return T;
@@ -824,10 +888,10 @@ static double ratio_track(const prim_t* P, const double* wt, int64_t n, double r
  * the sign of the chosen coefficient.  For 0 <= kappa <= kbar this is Woodcock
  * tracking with unit weights.  Returns 1 on a real collision at *tout, 0 on
  * escape. */
-static int delta_track(const prim_t* P, const double* wt, int64_t n, double rho, double r, const double* ray,
+static int delta_track(const prim_t* P, const double* wt, int64_t n, double rho, const double* ray, double lod_k,
                        rng_t* g, chords_t* C, double* tout, double* w)
 {
-    collect_chords(P, wt, n, r, ray, C);
+    collect_chords(P, wt, n, ray, lod_k, C);
     for (int64_t e = 0; e + 1 < C->nev; ++e) {
         double a = C->ev[e], b = C->ev[e + 1];
         if (!(b > a)) continue;
@@ -837,7 +901,7 @@ static int delta_track(const prim_t* P, const double* wt, int64_t n, double rho,
         for (;;) {
             t += -log(rng_u(g)) / kb;
             if (t >= b) break;
-            double k = piece_density(P, wt, C, rho, r, ray, t);
+            double k = piece_density(P, wt, C, rho, ray, t);
             double xi = rng_u(g);
             if (k >= 0.0) {
                 if (xi * kb < k) { *tout = t; return 1; }
@@ -855,11 +919,78 @@ static int delta_track(const prim_t* P, const double* wt, int64_t n, double rho,
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Free flight by inverting the cumulative distribution (Sec. 3, the          */
+/* CDF-inversion equation log(1 - xi) = -sum_i tau_i(x0, x_t); Sec. 4.4,       */
+/* distance sampling by a bisection solver).  With s = -log(1 - xi):          */
+/*   - escape when the optical depth of the whole segment [tmin, t_end] is     */
+/*     below s (t_end = the last chord exit);                                 */
+/*   - otherwise bisect [lo, hi] = [tmin, t_end] keeping tau(tmin, lo) < s <=  */
+/*     tau(tmin, hi): the optical depth of [lo, mid] decides which half holds  */
+/*     the crossing, until hi - lo <= 1e-6 (1 + |hi|); the collision is the    */
+/*     midpoint of the last bracket.                                          */
+/* Every optical depth is the sum of the closed-form segment integrals of the */
+/* chords (Sec. 4.4).  For a positive density the distance follows            */
+/* 1 - exp(-tau(tmin, t)) exactly; where the mixture is negative the           */
+/* cumulative depth is not monotone and the sampler returns one crossing (the */
+/* paper relies on the mixture being positive).                               */
+/* ------------------------------------------------------------------------- */
+#define FF_TOL 1e-6
+
+static double tau_between(const prim_t* P, const double* wt, const chords_t* C, double rho, const double* ray,
+                          double a, double b)
+{
+    double sub[8] = {ray[0], ray[1], ray[2], ray[3], ray[4], ray[5], a, b};
+    double acc = 0.0;
+    for (int64_t k = 0; k < C->nch; ++k) {
+        const chord_t* c = &C->ch[k];
+        if (c->tout <= a || c->tin >= b) continue;
+        hit_t H;
+        if (!hit_geom(&P[c->i], sub, &H)) continue;
+        acc += wt[c->i] * P[c->i].alpha * seg_integral(&P[c->i], &H);
+    }
+    return rho * acc;
+}
+
+static int analytic_flight(const prim_t* P, const double* wt, int64_t n, double rho, const double* ray, double lod_k,
+                           rng_t* g, chords_t* C, double* tout)
+{
+    collect_chords(P, wt, n, ray, lod_k, C);
+    double xi = rng_u(g);
+    double s = -log(1.0 - xi);
+    if (C->nch == 0) return 0;
+    double lo = ray[6], hi = C->ev[C->nev - 1];
+    if (tau_between(P, wt, C, rho, ray, lo, hi) < s) return 0;
+    double acc = 0.0;
+    while (hi - lo > FF_TOL * (1.0 + fabs(hi))) {
+        double mid = 0.5 * (lo + hi);
+        double d = tau_between(P, wt, C, rho, ray, lo, mid);
+        if (acc + d >= s) {
+            hi = mid;
+        } else {
+            acc += d;
+            lo = mid;
+        }
+    }
+    *tout = 0.5 * (lo + hi);
+    return 1;
+}
+
+/* exact transmittance exp(-tau) of a segment under the weights wt */
+static double exact_T(const prim_t* P, const double* wt, int64_t n, double rho, const double* ray, double lod_k,
+                      chords_t* C)
+{
+    collect_chords(P, wt, n, ray, lod_k, C);
+    if (C->nch == 0) return 1.0;
+    return exp(-tau_between(P, wt, C, rho, ray, ray[6], C->ev[C->nev - 1]));
+}
+
 void or_ratio_T(const double* params, int64_t n, double rho, double r, const double* rays, int64_t nr,
-                uint64_t cells, const uint32_t* bits, int spp, uint64_t seed, double* T_mean, double* T_var)
+                uint64_t cells, const uint32_t* bits, double lod_k, int spp, uint64_t seed, double* T_mean,
+                double* T_var)
 {
     prim_t* P = (prim_t*)malloc(sizeof(prim_t) * (n ? n : 1));
-    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i]);
+    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i], r, rho);
     double* wt = mask_weights(params, n, cells, bits);
 #pragma omp parallel
     {
@@ -870,7 +1001,7 @@ void or_ratio_T(const double* params, int64_t n, double rho, double r, const dou
             for (int sidx = 0; sidx < spp; ++sidx) {
                 rng_t g;
                 rng_init(&g, seed, (uint32_t)k, (uint32_t)sidx);
-                double T = ratio_track(P, wt, n, rho, r, rays + 8 * k, &g, &C);
+                double T = ratio_track(P, wt, n, rho, rays + 8 * k, lod_k, &g, &C);
                 s1 += T;
                 s2 += T * T;
             }
@@ -884,12 +1015,14 @@ void or_ratio_T(const double* params, int64_t n, double rho, double r, const dou
     free(P);
 }
 
-/* free-flight samples: t (or +inf on escape) and weight, spp per ray */
+/* free-flight samples: t (or +inf on escape) and weight, spp per ray;
+ * mode 0 weighted delta tracking, 1 CDF inversion by bisection */
 void or_free_flight(const double* params, int64_t n, double rho, double r, const double* rays, int64_t nr,
-                    uint64_t cells, const uint32_t* bits, int spp, uint64_t seed, double* t_out, double* w_out)
+                    uint64_t cells, const uint32_t* bits, int mode, int spp, uint64_t seed, double* t_out,
+                    double* w_out)
 {
     prim_t* P = (prim_t*)malloc(sizeof(prim_t) * (n ? n : 1));
-    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i]);
+    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i], r, rho);
     double* wt = mask_weights(params, n, cells, bits);
 #pragma omp parallel
     {
@@ -900,8 +1033,9 @@ void or_free_flight(const double* params, int64_t n, double rho, double r, const
                 rng_t g;
                 rng_init(&g, seed, (uint32_t)k, (uint32_t)sidx);
                 double t = INFINITY, w = 1.0;
-                if (!delta_track(P, wt, n, rho, r, rays + 8 * k, &g, &C, &t, &w)) t = INFINITY;
-                t_out[k * spp + sidx] = t;
+                int hit = mode ? analytic_flight(P, wt, n, rho, rays + 8 * k, 0.0, &g, &C, &t)
+                               : delta_track(P, wt, n, rho, rays + 8 * k, 0.0, &g, &C, &t, &w);
+                t_out[k * spp + sidx] = hit ? t : INFINITY;
                 w_out[k * spp + sidx] = w;
             }
         free(C.ch);
@@ -955,57 +1089,217 @@ void or_hg_cos(double g, int64_t n, uint64_t seed, double* out)
     }
 }
 
-/* Per-segment stochastic mask (uniform + control variate over levels,
- * orientation bins drawn from an even mixture of importance and uniform
- * sampling, Appendix B tables): level 0 always with weight 1; level l in
- * {1,2,3} with probability 1/3; bin k with probability
- * p_k = w_k / (2 W) + 1/6, w_k = exp(-fbar_{l,k}^2 a_k^2 / 2), a_k = |v.e_k|,
- * W = sum_k w_k; the drawn cell gets weight 3 / p_k (at most 18).  The w_k
- * are scaled by their maximum first (p_k does not change) so that W never
- * underflows. */
-static void stochastic_weights(const int32_t* cell, int64_t n, const double* med12, const double* v, rng_t* g,
-                               double* wt)
+/* ------------------------------------------------------------------------- */
+/* Per-segment stochastic masks (Sec. 4.5.1 stochastic Laplacian path         */
+/* tracing, Sec. 4.5.2 stochastic orientation-selective path tracing, Sec. 4.5 */
+/* implementation steps 1-5; Appendix B tables of frequency-level and         */
+/* orientation-bin strategies).  P = 4 levels (level 0 the low-pass level),   */
+/* K = 3 orientation bins with representative directions o_k = e_k.  A       */
+/* segment draws four uniforms: u[0] for the level strategy, u[l] for the bin */
+/* strategy of level l (l = 1..3).  Output: a weight per cell (level, bin);    */
+/* 0 when the cell is not traced.  Each cell's expected weight is 1 for the   */
+/* stochastic strategies (the segment's optical depth is unbiased); the       */
+/* threshold strategies drop cells deterministically.                         */
+/*                                                                           */
+/* Level strategies (frequency-level table; beta the power-law shape, the     */
+/* power law x = u^(1 / (1 - beta)) falls in bucket [a, b) of width 1/P, whose */
+/* probability is b^(1-beta) - a^(1-beta)):                                  */
+/*   0 deterministic: every level, weight 1;                                  */
+/*   1 uniform: one level l = floor(P u), weight P;                           */
+/*   2 power law: level floor(P x), weight 1 / (b^(1-beta) - a^(1-beta));     */
+/*   3 uniform + control variate: level 0 weight 1; one of levels 1..P-1      */
+/*     uniformly, weight P - 1;                                               */
+/*   4 power law + control variate: level 0 weight 1; level 1 + floor((P-1) x) */
+/*     over P - 1 buckets of width 1/(P-1), weight 1 / (b^(1-beta) - a^(1-beta));*/
+/*   5 power law + control variate, accumulating: k = floor(P x); levels       */
+/*     0..k traced, level j with weight 1 / (1 - (j/P)^(1-beta)).             */
+/* Bin strategies (orientation table; a_k = |v.o_k| / |v|, w_k =              */
+/* exp(-f0^2 a_k^2 / 2) with f0 the median |k_W| of cell (l, k), W = sum w_k,  */
+/* delta the alignment threshold), applied to each traced level l >= 1 (the   */
+/* low-pass level has no orientation and keeps weight 1):                     */
+/*   0 deterministic: every bin, weight 1;                                    */
+/*   1 threshold culling: bins with a_k <= delta, weight 1;                    */
+/*   2 uniform: one bin floor(K u), weight K;                                 */
+/*   3 importance: bin k with probability w_k / W, weight W / w_k;            */
+/*   4 threshold + uniform: bins with a_k <= delta weight 1, and one of the    */
+/*     N_above others uniformly, weight N_above;                              */
+/*   5 mixture (not in the paper): probability p_k = w_k / (2W) + 1 / (2K),    */
+/*     weight 1 / p_k (at most 2K).                                           */
+/* The w_k are scaled by their largest value first, which changes neither     */
+/* w_k / W nor W / w_k and keeps W from underflowing.                         */
+/* ------------------------------------------------------------------------- */
+#define NLEV 4
+#define NBIN 3
+
+static void level_weights(int strat, double beta, double u, double lw[NLEV])
 {
-    double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    double ul = rng_u(g), ub = rng_u(g);
-    int l = 1 + (int)(ul * 3.0);
-    if (l > 3) l = 3;
-    double lw[3], mx = -HUGE_VAL;
-    for (int k = 0; k < 3; ++k) {
-        double a = fabs(v[k]) / vn, fb = med12[l * 3 + k];
-        lw[k] = -0.5 * fb * fb * a * a;
-        if (lw[k] > mx) mx = lw[k];
+    double e = 1.0 - beta;
+    for (int l = 0; l < NLEV; ++l) lw[l] = 0.0;
+    if (strat == 0) {
+        for (int l = 0; l < NLEV; ++l) lw[l] = 1.0;
+    } else if (strat == 1) {
+        int l = (int)floor(NLEV * u);
+        if (l > NLEV - 1) l = NLEV - 1;
+        lw[l] = (double)NLEV;
+    } else if (strat == 2) {
+        double x = pow(u, 1.0 / e);
+        int l = (int)floor(NLEV * x);
+        if (l > NLEV - 1) l = NLEV - 1;
+        double a = (double)l / NLEV, b = (double)(l + 1) / NLEV;
+        lw[l] = 1.0 / (pow(b, e) - pow(a, e));
+    } else if (strat == 3) {
+        lw[0] = 1.0;
+        int j = (int)floor((NLEV - 1) * u);
+        if (j > NLEV - 2) j = NLEV - 2;
+        lw[1 + j] = (double)(NLEV - 1);
+    } else if (strat == 4) {
+        lw[0] = 1.0;
+        double x = pow(u, 1.0 / e);
+        int j = (int)floor((NLEV - 1) * x);
+        if (j > NLEV - 2) j = NLEV - 2;
+        double a = (double)j / (NLEV - 1), b = (double)(j + 1) / (NLEV - 1);
+        lw[1 + j] = 1.0 / (pow(b, e) - pow(a, e));
+    } else {
+        double x = pow(u, 1.0 / e);
+        int k = (int)floor(NLEV * x);
+        if (k > NLEV - 1) k = NLEV - 1;
+        for (int j = 0; j <= k; ++j) lw[j] = 1.0 / (1.0 - pow((double)j / NLEV, e));
     }
-    double wk[3], W = 0.0, pk[3];
-    for (int k = 0; k < 3; ++k) {
-        wk[k] = exp(lw[k] - mx);
-        W += wk[k];
-    }
-    for (int k = 0; k < 3; ++k) pk[k] = 0.5 * wk[k] / W + 1.0 / 6.0;
-    int k = 0;
-    double acc = pk[0];
-    while (k < 2 && ub >= acc) { ++k; acc += pk[k]; }
-    int pick = l * 3 + k;
-    double wpick = 3.0 / pk[k];
-    for (int64_t i = 0; i < n; ++i) wt[i] = (cell[i] < 3) ? 1.0 : (cell[i] == pick ? wpick : 0.0);
 }
 
-/* desc: [spp, multiple, max_scatter, albedo, hg_g, L_env, stochastic]
- * Single scattering: a camera ray is free-flight sampled; on escape it
- * returns w L_env; on a real collision w albedo T_ratio(x, w_iso) L_env.
- * Multiple scattering: repeat free flights, albedo and HG per collision,
- * terminate with 0 when a collision happens after max_scatter scatterings.
- * primary_T: ratio-tracked transmittance of the camera segment under the
- * segment's mask. */
+/* index of the bin drawn by u from probabilities p (the last bin with p > 0
+ * when rounding leaves u above the cumulative sum) */
+static int draw_bin(const double p[NBIN], double u)
+{
+    double acc = 0.0;
+    int last = -1;
+    for (int k = 0; k < NBIN; ++k) {
+        if (!(p[k] > 0.0)) continue;
+        last = k;
+        acc += p[k];
+        if (u < acc) return k;
+    }
+    return last;
+}
+
+static void bin_weights(int strat, double delta, const double f0[NBIN], const double a[NBIN], double u,
+                        double bw[NBIN])
+{
+    for (int k = 0; k < NBIN; ++k) bw[k] = 0.0;
+    if (strat == 0) {
+        for (int k = 0; k < NBIN; ++k) bw[k] = 1.0;
+    } else if (strat == 1) {
+        for (int k = 0; k < NBIN; ++k) bw[k] = a[k] <= delta ? 1.0 : 0.0;
+    } else if (strat == 2) {
+        int k = (int)floor(NBIN * u);
+        if (k > NBIN - 1) k = NBIN - 1;
+        bw[k] = (double)NBIN;
+    } else if (strat == 4) {
+        int above[NBIN], na = 0;
+        for (int k = 0; k < NBIN; ++k) {
+            if (a[k] <= delta) bw[k] = 1.0;
+            else above[na++] = k;
+        }
+        if (na > 0) {
+            int j = (int)floor(na * u);
+            if (j > na - 1) j = na - 1;
+            bw[above[j]] = (double)na;
+        }
+    } else {
+        double lw[NBIN], mx = -HUGE_VAL, w[NBIN], W = 0.0, p[NBIN];
+        for (int k = 0; k < NBIN; ++k) {
+            lw[k] = -0.5 * f0[k] * f0[k] * a[k] * a[k];
+            if (lw[k] > mx) mx = lw[k];
+        }
+        for (int k = 0; k < NBIN; ++k) {
+            w[k] = exp(lw[k] - mx);
+            W += w[k];
+        }
+        for (int k = 0; k < NBIN; ++k) p[k] = strat == 3 ? w[k] / W : 0.5 * w[k] / W + 0.5 / NBIN;
+        int k = draw_bin(p, u);
+        bw[k] = 1.0 / p[k];
+    }
+}
+
+/* cell weights of one segment with direction v from the four uniforms u */
+static void segment_cell_weights(int lstrat, int bstrat, double beta, double delta, const double med12[12],
+                                 const double v[3], const double u[4], double wc[12])
+{
+    double lw[NLEV];
+    level_weights(lstrat, beta, u[0], lw);
+    double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double a[NBIN] = {fabs(v[0]) / vn, fabs(v[1]) / vn, fabs(v[2]) / vn};
+    for (int l = 0; l < NLEV; ++l) {
+        double bw[NBIN] = {1.0, 1.0, 1.0};
+        if (l > 0 && lw[l] != 0.0) bin_weights(bstrat, delta, med12 + NBIN * l, a, u[l], bw);
+        for (int k = 0; k < NBIN; ++k) wc[NBIN * l + k] = lw[l] * bw[k];
+    }
+}
+
+/* test entry: cell weights for explicit uniforms.  strat = [level strategy,
+ * bin strategy, beta, delta] */
+void or_segment_cell_weights(const double* strat, const double* med12, const double* v, const double* u,
+                             double* wc12)
+{
+    segment_cell_weights((int)strat[0], (int)strat[1], strat[2], strat[3], med12, v, u, wc12);
+}
+
+/* test entry: n draws of the cell weights from the oracle's own streams
+ * (seed, draw index, 0) for direction v */
+void or_sample_cell_weights(const double* strat, const double* med12, const double* v, int64_t n, uint64_t seed,
+                            double* wc)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        rng_t g;
+        rng_init(&g, seed, (uint32_t)k, 0);
+        double u[4];
+        for (int m = 0; m < 4; ++m) u[m] = rng_u(&g);
+        segment_cell_weights((int)strat[0], (int)strat[1], strat[2], strat[3], med12, v, u, wc + 12 * k);
+    }
+}
+
+/* per-primitive weights of a segment: cell weight times the fixed mask */
+static void draw_segment_weights(const int32_t* cell, const double* wfix, int64_t n, int lstrat, int bstrat,
+                                 double beta, double delta, const double* med12, const double* v, rng_t* g,
+                                 double* wt)
+{
+    double u[4], wc[12];
+    for (int m = 0; m < 4; ++m) u[m] = rng_u(g);
+    segment_cell_weights(lstrat, bstrat, beta, delta, med12, v, u, wc);
+    for (int64_t i = 0; i < n; ++i) wt[i] = wfix[i] * wc[cell[i]];
+}
+
+/* desc: [0 spp, 1 multiple, 2 max_scatter, 3 albedo, 4 hg_g, 5 L_env,
+ *        6 stochastic, 7 level strategy, 8 bin strategy, 9 beta, 10 delta,
+ *        11 free flight (0 delta tracking, 1 CDF inversion),
+ *        12 shadow cells (0: the shadow segment's own mask), 13 lod_k]
+ * Every segment (camera, shadow, scattered) traces the fixed mask, or with
+ * stochastic != 0 draws its own cell weights by the two strategies for its
+ * direction.  Single scattering: the camera segment is free-flight sampled;
+ * on escape it returns w L_env; on a real collision w albedo T(x, w_iso) L_env
+ * with w_iso uniform on the sphere (a shadow ray toward the constant
+ * environment; with shadow cells != 0 it is traced against those cells only:
+ * the Zero-NEE strategy of Sec. 4.5 implementation details traces shadow rays
+ * against the low-pass level).  Multiple scattering: repeat free flights,
+ * albedo and HG per collision, terminate with 0 when a collision happens
+ * after max_scatter scatterings.
+ * Free flight 0: weighted delta tracking; transmittances by ratio tracking.
+ * Free flight 1: CDF inversion; transmittances exp(-tau) from the closed form.
+ * primary_T: the camera segment's transmittance estimate.  lod_k: the
+ * continuous-LOD cutoff of the camera segment (see lod_keep). */
 void or_render(const double* params, int64_t n, double rho, double r, const double* rays, int64_t nr,
                uint64_t cells, const uint32_t* bits, const double* desc, uint64_t seed, double* L_mean,
                double* L_var, double* T_mean, double* T_var)
 {
     int spp = (int)desc[0], multiple = (int)desc[1], max_sc = (int)desc[2], stoch = (int)desc[6];
     double albedo = desc[3], hg = desc[4], Lenv = desc[5];
+    int lstrat = (int)desc[7], bstrat = (int)desc[8], ff = (int)desc[11];
+    double beta = desc[9], delta = desc[10], lod_k = desc[13];
+    uint64_t shadow_cells = (uint64_t)desc[12];
     prim_t* P = (prim_t*)malloc(sizeof(prim_t) * (n ? n : 1));
-    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i]);
+    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i], r, rho);
     double* wfix = mask_weights(params, n, cells, bits);
+    double* wshadow = mask_weights(params, n, shadow_cells & cells, bits);
     int32_t* cell = (int32_t*)malloc(sizeof(int32_t) * (n ? n : 1));
     or_cells(params, n, cell, NULL);
     double med12[12];
@@ -1027,16 +1321,23 @@ void or_render(const double* params, int64_t n, double rho, double r, const doub
                 for (int seg = 0;; ++seg) {
                     const double* wt = wfix;
                     if (stoch) {
-                        stochastic_weights(cell, n, med12, ray + 3, &g, wseg);
+                        draw_segment_weights(cell, wfix, n, lstrat, bstrat, beta, delta, med12, ray + 3, &g, wseg);
                         wt = wseg;
                     }
+                    double lk = seg == 0 ? lod_k : 0.0;
                     if (seg == 0) {
-                        rng_t gT;
-                        rng_init(&gT, seed ^ 0x5bd1e9955bd1e995ull, (uint32_t)k, (uint32_t)sidx);
-                        Tprim = ratio_track(P, wt, n, rho, r, ray, &gT, &C);
+                        if (ff) {
+                            Tprim = exact_T(P, wt, n, rho, ray, lk, &C);
+                        } else {
+                            rng_t gT;
+                            rng_init(&gT, seed ^ 0x5bd1e9955bd1e995ull, (uint32_t)k, (uint32_t)sidx);
+                            Tprim = ratio_track(P, wt, n, rho, ray, lk, &gT, &C);
+                        }
                     }
                     double t;
-                    if (!delta_track(P, wt, n, rho, r, ray, &g, &C, &t, &w)) {
+                    int hit = ff ? analytic_flight(P, wt, n, rho, ray, lk, &g, &C, &t)
+                                 : delta_track(P, wt, n, rho, ray, lk, &g, &C, &t, &w);
+                    if (!hit) {
                         L += w * Lenv;
                         break;
                     }
@@ -1045,7 +1346,17 @@ void or_render(const double* params, int64_t n, double rho, double r, const doub
                         double d[3];
                         sample_sphere(&g, d);
                         double sray[8] = {x[0], x[1], x[2], d[0], d[1], d[2], 0.0, INFINITY};
-                        L += w * albedo * ratio_track(P, wt, n, rho, r, sray, &g, &C) * Lenv;
+                        const double* ws = wshadow;
+                        if (!shadow_cells) {
+                            ws = wfix;
+                            if (stoch) {
+                                draw_segment_weights(cell, wfix, n, lstrat, bstrat, beta, delta, med12, d, &g, wseg);
+                                ws = wseg;
+                            }
+                        }
+                        double Ts = ff ? exact_T(P, ws, n, rho, sray, 0.0, &C)
+                                       : ratio_track(P, ws, n, rho, sray, 0.0, &g, &C);
+                        L += w * albedo * Ts * Lenv;
                         break;
                     }
                     if (nsc >= max_sc) break;
@@ -1073,6 +1384,7 @@ void or_render(const double* params, int64_t n, double rho, double r, const doub
         free(C.ev);
     }
     free(cell);
+    free(wshadow);
     free(wfix);
     free(P);
 }
@@ -1089,8 +1401,9 @@ void or_render(const double* params, int64_t n, double rho, double r, const doub
 /* The t-moments reduce to J_k = int u^k e^{-u^2/2 + i Omega u} du:           */
 /*   J1 = -[e] + i Omega J0,  J2 = -[u e] + J0 + i Omega J1.                 */
 /* ------------------------------------------------------------------------- */
-static void hit_grad(const prim_t* P, const hit_t* H, const double* ray, double r, double scale, double* g15)
+static void hit_grad(const prim_t* P, const hit_t* H, const double* ray, double scale, double* g15)
 {
+    const double r = P->rr; /* a clamped radius is held fixed (its own derivative is left out) */
     const double* v = ray + 3;
     double n = H->n, Om = H->Om;
     double ua = H->ua, ub = H->ub;
@@ -1170,10 +1483,10 @@ static void hit_grad(const prim_t* P, const hit_t* H, const double* ray, double 
 
 /* grad (n x 15) = sum_rays dL/dtau_r * dtau_r/dparams; tau_r = rho sum alpha_i I_i */
 void or_tau_grad(const double* params, int64_t n, double rho, double r, const double* rays, int64_t nr,
-                 uint64_t cells, const uint32_t* bits, const double* dL_dtau, double* grad)
+                 uint64_t cells, const uint32_t* bits, double lod_k, const double* dL_dtau, double* grad)
 {
     prim_t* P = (prim_t*)malloc(sizeof(prim_t) * (n ? n : 1));
-    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i]);
+    for (int64_t i = 0; i < n; ++i) prim_decode(params + 15 * i, &P[i], r, rho);
     double* wt = mask_weights(params, n, cells, bits);
     memset(grad, 0, sizeof(double) * 15 * (size_t)n);
 #pragma omp parallel for schedule(dynamic, 16)
@@ -1183,10 +1496,11 @@ void or_tau_grad(const double* params, int64_t n, double rho, double r, const do
         for (int64_t k = 0; k < nr; ++k) {
             const double* ray = rays + 8 * k;
             if (dL_dtau[k] == 0.0) continue;
-            if (sphere_reject(&P[i], ray, r)) continue;
+            if (sphere_reject(&P[i], ray)) continue;
             hit_t H;
-            if (!hit_geom(&P[i], ray, r, &H)) continue;
-            hit_grad(&P[i], &H, ray, r, rho * dL_dtau[k], g15);
+            if (!hit_geom(&P[i], ray, &H)) continue;
+            if (!lod_keep(&P[i], &H, ray, lod_k)) continue; /* the cutoff itself is held fixed */
+            hit_grad(&P[i], &H, ray, rho * dL_dtau[k], g15);
         }
         memcpy(grad + 15 * i, g15, sizeof(g15));
     }

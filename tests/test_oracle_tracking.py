@@ -132,21 +132,28 @@ def test_furnace_signed_density_in_mean(orc):
     assert pooled < 3.0 and worst < 4.5
 
 
-@pytest.mark.slow
-def test_single_scattering_matches_nested_quadrature(orc):
-    """L = T(0,inf) L_env + albedo int T(0,t) kappa(t) [int p(w) T(x_t, w) dw] dt L_env,
-    isotropic p, positive kernels; t by Gauss-Legendre per chord piece, directions
-    by a 3000-point Fibonacci sphere."""
+def _quadrature_scene(n_gabor=0):
     g = np.random.default_rng(4)
-    params = np.zeros((6, 15))
-    params[:, 0:3] = 0.5 + 0.08 * g.standard_normal((6, 3))
-    q = g.standard_normal((6, 4))
+    n = 6 + n_gabor
+    params = np.zeros((n, 15))
+    params[:, 0:3] = 0.5 + 0.08 * g.standard_normal((n, 3))
+    q = g.standard_normal((n, 4))
     params[:, 3:7] = q / np.linalg.norm(q, axis=1, keepdims=True)
-    params[:, 7:10] = g.uniform(0.05, 0.09, (6, 3))
-    params[:, 14] = g.uniform(0.5, 1.5, 6)
-    rho, albedo = 0.02, 0.9
-    ray = np.array([0.5, 0.5, -0.5, 0.05, -0.02, 1.0, 0.0, np.inf])
-    ray[3:6] /= np.linalg.norm(ray[3:6])
+    params[:, 7:10] = g.uniform(0.05, 0.09, (n, 3))
+    params[:, 14] = g.uniform(0.5, 1.5, n)
+    if n_gabor:
+        # Gabor kernels of the top frequency level on top of the Gaussians
+        f = g.standard_normal((n_gabor, 3))
+        params[6:, 10:13] = 2.0 * f / np.linalg.norm(f, axis=1, keepdims=True)
+        params[6:, 13] = 0.0
+    return params
+
+
+def _single_scattering_reference(orc, params, ray, rho, albedo, shadow_cells=None):
+    """L = T(0,inf) L_env + albedo int T(0,t) kappa(t) [int p(w) T_s(x_t, w) dw] dt L_env,
+    isotropic p; T_s the shadow transmittance (of the cells shadow_cells when
+    given); t by Gauss-Legendre per chord piece, directions by a 3000-point
+    Fibonacci sphere."""
     # chord ends of every truncated ellipsoid along the camera ray (numpy geometry)
     brk = [0.0]
     for p in params:
@@ -181,11 +188,106 @@ def test_single_scattering_matches_nested_quadrature(orc):
     sr[:, 0:3] = np.repeat(pts[sel], m, axis=0)
     sr[:, 3:6] = np.tile(dirs, (len(sel), 1))
     sr[:, 6], sr[:, 7] = 0.0, np.inf
-    Ts = np.exp(-orc.tau(params, sr, rho=rho)[0]).reshape(len(sel), m)
+    cells = orc.FULL_MASK if shadow_cells is None else shadow_cells
+    Ts = np.exp(-orc.tau(params, sr, rho=rho, cells=cells)[0]).reshape(len(sel), m)
     inner[sel] = Ts.mean(axis=1)
     Tinf = math.exp(-orc.tau(params, ray[None, :], rho=rho)[0][0])
-    L_ref = Tinf + albedo * np.sum(ws * T0 * kap * inner)
-    spp = 40000
-    L, Lv, _, _ = orc.render(params, ray[None, :], spp, seed=8, rho=rho, multiple=False, albedo=albedo)
+    return Tinf + albedo * np.sum(ws * T0 * kap * inner)
+
+
+_QRAY = np.array([0.5, 0.5, -0.5, 0.05, -0.02, 1.0, 0.0, np.inf])
+_QRAY[3:6] /= np.linalg.norm(_QRAY[3:6])
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("analytic", [False, True])
+def test_single_scattering_matches_nested_quadrature(orc, analytic):
+    """positive kernels: delta tracking and CDF inversion (with exact shadow
+    transmittance) both solve the single-scattering transfer equation"""
+    params = _quadrature_scene()
+    rho, albedo = 0.02, 0.9
+    L_ref = _single_scattering_reference(orc, params, _QRAY, rho, albedo)
+    spp = 40000 if not analytic else 20000
+    L, Lv, _, _ = orc.render(params, _QRAY[None, :], spp, seed=8, rho=rho, multiple=False, albedo=albedo,
+                             analytic=analytic)
     se = math.sqrt(Lv[0] / spp)
     assert abs(L[0] - L_ref) < 4 * se + 2e-4
+
+
+@pytest.mark.slow
+def test_zero_nee_matches_nested_quadrature(orc):
+    """shadow rays traced against the low-pass level only (Zero-NEE, Sec. 4.5
+    implementation details): the estimator converges to the transfer equation
+    with the shadow transmittance of level 0, and differs from the full one"""
+    params = _quadrature_scene(n_gabor=4)
+    c, _ = orc.cells(params)
+    assert np.all(c[:6] == 0) and np.all(c[6:] >= 9)
+    rho, albedo = 0.03, 0.9
+    L_ref = _single_scattering_reference(orc, params, _QRAY, rho, albedo, shadow_cells=0b111)
+    L_full = _single_scattering_reference(orc, params, _QRAY, rho, albedo)
+    spp = 40000
+    L, Lv, _, _ = orc.render(params, _QRAY[None, :], spp, seed=9, rho=rho, multiple=False, albedo=albedo,
+                             shadow_cells=0b111)
+    se = math.sqrt(Lv[0] / spp)
+    assert abs(L[0] - L_ref) < 4 * se + 2e-4
+    assert abs(L_ref - L_full) > 8 * se
+
+
+def test_shadow_cells_full_is_the_default(orc):
+    params = gen.uniform_scene(64, 5)
+    rays = gen.ortho_rays(8, 8)
+    a = orc.render(params, rays, 16, seed=3, rho=0.01, multiple=False)
+    b = orc.render(params, rays, 16, seed=3, rho=0.01, multiple=False, shadow_cells=orc.FULL_MASK)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_analytic_free_flight_distribution_positive_gaussian(orc):
+    """CDF inversion by bisection: distances follow 1 - exp(-tau(0, t)) and
+    the escape probability is exp(-tau) (Kolmogorov-Smirnov), weights 1"""
+    params = _gaussian_prim()
+    ray = np.array([[0.52, 0.47, -0.5, 0.0, 0.0, 1.0, 0.0, np.inf]])
+    rho = 1.5 / orc.tau(params, ray, rho=1.0)[0][0]
+    tau_tot = orc.tau(params, ray, rho=rho)[0][0]
+    t, w = orc.free_flight(params, ray, 8000, seed=4, rho=rho, analytic=True)
+    assert np.all(w == 1.0)
+    t = t[0]
+    col = t[np.isfinite(t)]
+    esc = np.mean(~np.isfinite(t))
+    assert abs(esc - math.exp(-tau_tot)) < 4 * math.sqrt(math.exp(-tau_tot) * (1 - math.exp(-tau_tot)) / len(t))
+    ts = np.sort(col)[:: max(1, len(col) // 2000)]
+    rr = np.repeat(ray, len(ts), axis=0)
+    rr[:, 7] = ts
+    F = 1.0 - np.exp(-orc.tau(params, rr, rho=rho)[0])
+    ks = st.kstest(F / (1.0 - math.exp(-tau_tot)), "uniform")
+    assert ks.pvalue > 1e-3
+    # each distance solves tau(0, t) = -log(1 - xi) to the bisection tolerance:
+    # the optical depth up to the sampled point is an Exp(1) variate
+    # truncated at tau_tot, i.e. F above is uniform (checked) and every t lies
+    # where the density is non-zero
+    assert np.all(np.diff(F) >= 0)
+
+
+def test_analytic_furnace_positive_density_is_exact(orc):
+    params = gen.uniform_scene(64, 5).astype(np.float64)
+    params[:, 10:14] = 0.0
+    rays = gen.ortho_rays(16, 16)
+    L, _, T, _ = orc.render(params, rays, 8, seed=1, rho=0.05, multiple=True, max_scatter=100000, albedo=1.0,
+                            hg_g=0.3, analytic=True)
+    assert np.all(L == 1.0)
+    tau, _, _ = orc.tau(params, rays, rho=0.05)
+    assert np.allclose(T, np.exp(-tau), rtol=1e-12, atol=0)
+
+
+@pytest.mark.slow
+def test_analytic_and_delta_tracking_agree_on_positive_field(orc):
+    """multiple scattering on a positive field: both free-flight samplers are
+    unbiased for the same transfer equation"""
+    params = gen.uniform_scene(64, 5).astype(np.float64)
+    params[:, 10:14] = 0.0
+    rays = gen.ortho_rays(16, 16)[::9]
+    spp = 3000
+    a = orc.render(params, rays, spp, seed=5, rho=0.05, multiple=True, albedo=0.8, hg_g=0.3, analytic=True)
+    d = orc.render(params, rays, spp, seed=6, rho=0.05, multiple=True, albedo=0.8, hg_g=0.3)
+    pooled, worst = _pooled(a[0], d[0], np.sqrt((a[1] + d[1]) / spp))
+    assert pooled < 3.0 and worst < 4.5
