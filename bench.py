@@ -30,11 +30,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# bytes each unit of work must touch (per-unit figures; see the design notes)
-# optical depth: per ray, per child-box hit (half a 64 B node record), per chord
-# (a 60 B primitive record); tracking: per internal-node visit (its 64 B
-# record) and per primitive record read at a leaf
-RAY_BYTES, OUT_BYTES, PRIM_BYTES, NODE_BYTES, VISIT_BYTES = 32, 8, 60, 32, 64
+# VALU issue peak: 256 CUs x one wave64 instruction per cycle (4 SIMD16 units,
+# 4 cycles each) x 2.4 GHz; 64 lanes x 2 (FMA) x 614.4e9 = 78.6 TFLOP/s, the
+# float32 peak without packed instructions (which this build turns off)
+PEAK_VALU_INSTS = 256 * 2.4e9
+# bytes each unit of work must touch (the per-unit figures of the hot-path
+# table): optical depth per ray 32 (ray) + 8 (tau, T) + 60 per primitive with
+# a non-empty chord + 32 per box met (half a 64 B node record); tracking per
+# consumed tentative point 32 per node a point query visits + 60 per
+# primitive whose support contains the point, plus 40 per camera ray
+RAY_BYTES, OUT_BYTES, PRIM_BYTES, NODE_BYTES = 32, 8, 60, 32
 
 
 def log(*a):
@@ -56,6 +61,7 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
+    ap.add_argument("--bin", default="mixture", help="orientation-bin strategy of the multiple-scattering workload")
     return ap.parse_args()
 
 
@@ -72,6 +78,8 @@ def main():
     from gen import workloads as W
 
     torch.cuda.init()
+    if args.workload.startswith("blob1m"):
+        return multiple_scattering_bench(args)
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -113,7 +121,7 @@ def main():
             gf.gf_optical_depth(scene, rays, m, image_width=width)
             b.record()
             if args.render:
-                gf.gf_render(scene, rays, desc(m), image_width=width, want_var=False)
+                gf.gf_render_rays(scene, rays, desc(m), image_width=width, want_var=False)
             c.record()
             evs.append((a, b, c))
         if record is not None:
@@ -150,15 +158,16 @@ def main():
     # algorithmic work of the timed launches (same inputs and seeds)
     scene = gf.Scene(params, rho)
     masks, bits = masks_for(scene)
-    tau_bytes, ren_bytes = [], []
+    tau_bytes, ren_bytes, ren_counts = [], [], []
     for k, m in enumerate(masks):
         log("counting work of mask %s" % mask_names[k])
         nodes, hits = gf.gf_optical_depth_counts(scene, rays, m, image_width=width)
         nn, nh = int(nodes.sum().item()), int(hits.sum().item())
         tau_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + PRIM_BYTES * nh + NODE_BYTES * nn)
         if args.render:
-            tent, qn, qp, nwin = gf.gf_render_counts(scene, rays, desc(m), image_width=width)
-            ren_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + VISIT_BYTES * qn + PRIM_BYTES * qp)
+            c = gf.gf_render_counts(scene, rays, desc(m), image_width=width)
+            ren_counts.append(c)
+            ren_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + NODE_BYTES * c[5] + PRIM_BYTES * c[6])
         else:
             ren_bytes.append(0)
     torch.cuda.synchronize()
@@ -166,27 +175,37 @@ def main():
     ren_gbs = [b / (t * 1e-3) / 1e9 if t > 0 else 0.0 for b, t in zip(ren_bytes, ren_ms)]
     dominant = "render" if args.render and sum(ren_ms) >= sum(tau_ms) else "optical_depth"
     if dominant == "render":
-        ach = sum(ren_bytes) / (sum(ren_ms) * 1e-3) / 1e9
+        per_launch_s = sum(ren_ms) * 1e-3 / 4
+        alg = sum(ren_bytes) / 4
     else:
-        ach = sum(tau_bytes) / (sum(tau_ms) * 1e-3) / 1e9
+        per_launch_s = sum(tau_ms) * 1e-3 / 4
+        alg = sum(tau_bytes) / 4
+    ach = alg / per_launch_s / 1e9
+    prof = profile_figures(name, dominant)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, dominant),
-                "kernel": dominant}
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": prof.get("traffic"), "kernel": KERNELS[dominant],
+                "algorithmic_bytes_per_launch": int(alg), "launch_ms": round(1e3 * per_launch_s, 3)}
+    if prof.get("traffic"):
+        roofline["measured_frac"] = round(prof["traffic"] / per_launch_s / 1e9 / PEAK_HBM_GBS, 4)
+    if prof.get("valu_insts"):
+        roofline["valu_frac"] = round(prof["valu_insts"] / per_launch_s / PEAK_VALU_INSTS, 4)
 
     result = {
         "metric": "Mrays/s transmittance at full & masked LOD; p50/p99 render-request latency",
         "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (f64 geometry setup)", "data": "synthetic",
-        "config": {"workload": "%s: %d Gabors (64-blob field), %dx%d pinhole, masks %s%s"
-                   % (name, params.shape[0], width, width, "/".join(mask_names),
+        "config": {"workload": "%s: %s, %dx%d pinhole, masks %s%s"
+                   % (name, W.describe(name), width, width, "/".join(mask_names),
                       ", %d-spp single scattering" % args.spp if args.render else ", optical depth and transmittance"),
                    "global_batch": npix, "parallelism": "single GPU"},
         "roofline": roofline,
         "per_mask": {mask_names[k]: {"tau_ms": round(tau_ms[k], 3), "tau_Mrays_s": round(npix / tau_ms[k] / 1e3, 1),
                                      "tau_alg_GBs": round(tau_gbs[k], 1), "render_ms": round(ren_ms[k], 3),
                                      "render_Msamples_s": round(npix * spp_r / max(ren_ms[k], 1e-9) / 1e3, 2),
-                                     "render_alg_GBs": round(ren_gbs[k], 1)} for k in range(4)},
+                                     "render_alg_GBs": round(ren_gbs[k], 1),
+                                     "render_work_per_sample": work_per_sample(ren_counts, k, npix * spp_r)}
+                     for k in range(4)},
         "build_ms": round(float(np.mean(timings["build"])), 3),
     }
 
@@ -201,24 +220,180 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (profiles/<kernel>_<workload>_pmc.txt), scaled by the calibration
-    factors recorded there; None when no summary exists or the HIP sources
-    changed since it was taken."""
+KERNELS = {"render": "void k_render<false, false>", "optical_depth": "void k_tau<false>"}
+
+
+def work_per_sample(counts, k, samples):
+    if not counts or not samples:
+        return None
+    c = counts[k]
+    names = ["tentative_points", "kernel_node_visits", "kernel_prim_reads", "windows", "points_used",
+             "point_query_nodes", "covering_prims"]
+    return {n: round(v / samples, 2) for n, v in zip(names, c)}
+
+
+def profile_figures(workload, kernel):
+    """Per-launch figures of the dominant kernel from the committed rocprofv3
+    summaries, used only while their recorded source hash matches the HIP
+    sources: measured HBM bytes (profiles/<kernel>_<workload>_pmc.txt,
+    FETCH_SIZE and WRITE_SIZE scaled by the calibration factors recorded
+    there) and VALU instructions (profiles/<kernel>_<workload>_sq.txt)."""
     sys.path.insert(0, ROOT)
     import profile_summary
-    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, workload))
-    if not os.path.exists(path):
-        return None
-    text = open(path).read().splitlines()
-    if not any(l.startswith("# source hash: %s" % profile_summary.source_hash()) for l in text):
-        return None
-    name = {"optical_depth": "void k_tau<false>", "render": "void k_render<false>"}[kernel]
-    for line in text:
-        if line.startswith(name):
-            return int(float(line.split()[-1]) * 1e6)
-    return None
+    out = {}
+    name = KERNELS[kernel]
+    for kind in ("pmc", "sq"):
+        path = os.path.join(ROOT, "profiles", "%s_%s_%s.txt" % (kernel, workload, kind))
+        if not os.path.exists(path):
+            continue
+        text = open(path).read().splitlines()
+        if not any(l.startswith("# source hash: %s" % profile_summary.source_hash()) for l in text):
+            continue
+        header = next((l for l in text if l.startswith("kernel ")), None)
+        for line in text:
+            if not line.startswith(name):
+                continue
+            if kind == "pmc":
+                out["traffic"] = int(float(line.split()[-1]) * 1e6)
+            elif header:
+                cols = header.split()
+                vals = line[48:].split()
+                if "SQ_INSTS_VALU" in cols:
+                    out["valu_insts"] = float(vals[cols.index("SQ_INSTS_VALU") - 1])
+            break
+    return out
+
+
+def multiple_scattering_bench(args):
+    """The 1M-primitive multiple-scattering workload: a 1024x1024 pinhole
+    frame, 4 spp, Henyey-Greenstein g = 0.3, albedo 0.9, up to 16 bounces,
+    per-segment stochastic masks (uniform + control variate levels, --bin
+    orientation strategy).  One step: scene build, optical depth of every
+    pixel at the full mask, the render.  Reports camera paths and
+    transmittance rays per second, the work per sample (counted on a
+    64-row band at the frame's centre), and the primary transmittance's
+    bias and variance against the full-mask FP64 optical depth of a
+    4096-pixel subset (in the CPU leg)."""
+    import numpy as np
+    import torch
+
+    import paper_2602_05081_amd as gf
+    from gen import workloads as W
+
+    name, spp = args.workload, 4
+    params_h, rays_h, rho = W.scene(name), W.rays(name), W.rho(name)
+    width = int(math.isqrt(rays_h.shape[0]))
+    params, rays = torch.as_tensor(params_h).cuda(), torch.as_tensor(rays_h).cuda()
+    npix = rays.shape[0]
+    desc = gf.render_desc(spp=spp, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, env=1.0, stochastic=True,
+                          level="uniform_cv", bin=args.bin, seed=4321)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    rec = []
+    out = None
+    t0 = None
+    for k in range(args.warmup + args.steps):
+        if k == args.warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        e = [ev() for _ in range(4)]
+        e[0].record()
+        scene = gf.Scene(params, rho)
+        e[1].record()
+        gf.gf_optical_depth(scene, rays, image_width=width)
+        e[2].record()
+        out = gf.gf_render_rays(scene, rays, desc, image_width=width)
+        e[3].record()
+        if k >= args.warmup:
+            rec.append(e)
+        torch.cuda.synchronize()
+        log("%s step %d done" % ("warmup" if k < args.warmup else "timed", k))
+        scene.close()
+    t1 = time.perf_counter()
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    build_ms = float(np.mean([a.elapsed_time(b) for a, b, c, d in rec]))
+    tau_ms = float(np.mean([b.elapsed_time(c) for a, b, c, d in rec]))
+    ren_ms = float(np.mean([c.elapsed_time(d) for a, b, c, d in rec]))
+    L, _, Tm, Tv = (x.cpu().numpy() for x in out)
+    units = npix * (1 + spp)
+    # work per sample on the central band (the counting variant also walks
+    # a point query per consumed point)
+    scene = gf.Scene(params, rho)
+    r0 = width // 2 - 32
+    band = rays[r0 * width:(r0 + 64) * width].contiguous()
+    log("counting work on a 64-row band")
+    c = gf.gf_render_counts(scene, band, desc, image_width=width)
+    band_samples = band.shape[0] * spp
+    alg_frame = npix * (RAY_BYTES + OUT_BYTES) + (NODE_BYTES * c[5] + PRIM_BYTES * c[6]) * (npix / band.shape[0])
+    ach = alg_frame / (ren_ms * 1e-3) / 1e9
+    prof = profile_figures(name, "render")
+    roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": prof.get("traffic"), "kernel": KERNELS["render"],
+                "algorithmic_bytes_per_launch": int(alg_frame), "launch_ms": round(ren_ms, 3),
+                "note": "algorithmic bytes counted on the central 64 rows, scaled to the frame"}
+    if prof.get("traffic"):
+        roofline["measured_frac"] = round(prof["traffic"] / (ren_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+    if prof.get("valu_insts"):
+        roofline["valu_frac"] = round(prof["valu_insts"] / (ren_ms * 1e-3) / PEAK_VALU_INSTS, 4)
+    result = {
+        "metric": "Mrays/s transmittance at full & masked LOD; p50/p99 render-request latency",
+        "value": round(units / (ms_per_step * 1e-3) / 1e6, 4), "unit": "Mrays/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f64 geometry setup)",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s, %dx%d pinhole, %d spp, multiple scattering (HG 0.3, albedo 0.9, <= 16 "
+                               "bounces), per-segment stochastic masks (uniform+CV levels, %s bins)"
+                               % (name, W.describe(name), width, width, spp, args.bin),
+                   "global_batch": npix, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "build_ms": round(build_ms, 2), "tau_ms": round(tau_ms, 2), "tau_Mrays_s": round(npix / tau_ms / 1e3, 2),
+        "render_ms": round(ren_ms, 1), "camera_paths_per_s": round(npix * spp / (ren_ms * 1e-3), 1),
+        "frame_mean_radiance": round(float(L.mean()), 5), "frame_mean_primary_T": round(float(Tm.mean()), 5),
+        "render_work_per_sample_band": {k: round(v / band_samples, 2) for k, v in zip(
+            ["tentative_points", "kernel_node_visits", "kernel_prim_reads", "windows", "points_used",
+             "point_query_nodes", "covering_prims"], c)},
+    }
+    if not args.no_cpu:
+        log("oracle on the host")
+        result["cpu_baseline"], result["primary_T_vs_full_mask"] = multiple_scattering_cpu(
+            args, np, params_h, rays_h, rho, Tm, Tv, spp, units, ms_per_step)
+    scene.close()
+    print(json.dumps(result), flush=True)
+
+
+def multiple_scattering_cpu(args, np, params, rays, rho, Tm, Tv, spp, units, ms_per_step):
+    """FP64 oracle on the host: a bounded sample of the workload (optical
+    depth of 64 rays, 8 rays x 4 spp of the multiple-scattering render with
+    the same strategies), scaled to one step; and the GPU's stochastic
+    primary transmittance against exp(-tau) of the full-mask FP64 optical
+    depth on a fixed 4096-pixel subset (bias and mean per-sample variance)."""
+    import oracle
+    from gen import workloads as W
+    sub = W.pixel_subset(rays.shape[0], k=64, seed=5)
+    t0 = time.perf_counter()
+    oracle.tau(params, rays[sub], rho=rho)
+    t_tau = (time.perf_counter() - t0) / len(sub)
+    sub_r = W.pixel_subset(rays.shape[0], k=8, seed=6)
+    t0 = time.perf_counter()
+    oracle.render(params, rays[sub_r], spp, seed=3, rho=rho, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3,
+                  stochastic=True, level="uniform_cv", bin=args.bin)
+    t_ren = (time.perf_counter() - t0) / (len(sub_r) * spp)
+    step_s = rays.shape[0] * (t_tau + spp * t_ren)
+    cores = min(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), os.cpu_count() or 1)
+    cpu = {"value": round(units / step_s / 1e6, 8), "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+           "sample": "%d optical-depth rays and %d rays x %d spp multiple scattering, scaled to one step"
+                     % (len(sub), len(sub_r), spp),
+           "tau_ms_per_ray": round(1e3 * t_tau, 3), "render_ms_per_sample": round(1e3 * t_ren, 2)}
+    bsub = W.pixel_subset(rays.shape[0], k=4096, seed=7)
+    log("full-mask optical depth of 4096 pixels (oracle)")
+    tau, _, _ = oracle.tau(params, rays[bsub], rho=rho)
+    ref = np.exp(-tau)
+    d = Tm[bsub].astype(np.float64) - ref
+    bias = {"pixels": len(bsub), "mean_T_gpu": round(float(Tm[bsub].mean()), 6),
+            "mean_T_full_mask": round(float(ref.mean()), 6), "bias": round(float(d.mean()), 6),
+            "bias_se": round(float(np.sqrt((Tv[bsub] / spp).sum()) / len(bsub)), 6),
+            "mean_abs_error": round(float(np.abs(d).mean()), 6),
+            "mean_sample_variance": round(float(Tv[bsub].mean()), 6)}
+    return cpu, bias
 
 
 def serving(args, gf, W, np, torch):

@@ -5,7 +5,8 @@
  * anisotropic Gabor kernels (paper: "Gabor Fields: Orientation-Selective
  * Level-of-Detail for Volume Rendering"; Sec. 3 for the extinction field,
  * optical depth and transmittance, Sec. 4.2 for the kernel, Sec. 4.4 for the
- * closed-form line integral, Sec. 4.5 for frequency / orientation masking).
+ * closed-form line integral, Sec. 4.5 for frequency / orientation masking,
+ * Sec. 4.6 for the implementation details).
  *
  * Conventions shared by every call
  * --------------------------------
@@ -23,7 +24,7 @@
  *   of the largest |f_k| (ties to the lower axis).  A gf_mask keeps primitive i
  *   when bit cell(i) of `cells` is set AND (prim_bits == NULL or bit i of
  *   prim_bits is set).  This follows the per-level visibility masks V_l = 2^l
- *   and the ray-mask AND of Sec. 4.5 (implementation details).
+ *   and the ray-mask AND of Sec. 4.6 (implementation details).
  * Pointers: every array argument documented "device" is device memory of the
  *   current HIP device, owned by the caller; the library never frees it.
  * Streams: `stream` is a hipStream_t (NULL = default stream).  Calls are
@@ -56,17 +57,30 @@ typedef struct gf_scene_s* gf_scene;
 typedef struct {
     float rho;          /* extinction scale multiplying every alpha (> 0) */
     float trunc_r;      /* Mahalanobis truncation radius r (Sec. 3: 3-sigma support); 0 -> 3 */
-    int majorant_grid;  /* majorant grid resolution G (G^3 voxels); 0 -> 64 */
+    int majorant_grid;  /* resolution G of an optional majorant grid (G^3 voxels x 12 cells, the
+                           point bound gf_density reports); 0 = none (the tracking kernels draw
+                           their own per-ray majorants and do not use it) */
+    float clamp_eps;    /* adaptive clamping (Sec. 4.4): each primitive's radius becomes min(r, E_i),
+                           E_i^2 = 2 ln(rho |alpha_i| s_max / (2 pi s0 s1 s2 eps)) (0 when E_i^2 <= 0):
+                           the Mahalanobis radius where the kernel's largest line integral across
+                           it falls below eps (the carrier, |cos| <= 1, left out).  It changes the
+                           density (a scene option).  0 = off. */
 } gf_scene_desc;
 
 typedef struct {
     uint64_t cells;            /* bit c keeps cell c (c = 3*level + bin); bits >= 12 ignored */
     const uint32_t* prim_bits; /* device, ceil(n/32) words, caller order; NULL = all */
+    float lod_k;               /* continuous LOD cutoff (supplementary "LOD Selection"): a primitive is
+                                  kept on a ray only when |f| d <= lod_k, d = |v| tc the distance from the
+                                  ray origin to the primitive's Mahalanobis-closest point (kept when
+                                  tc <= 0).  lod_k = R / (4 tan(fov/2)) puts the cutoff at the Nyquist
+                                  frequency of an R-pixel camera.  0 = off.  In gf_render it applies to
+                                  camera segments only. */
 } gf_mask;
 
 typedef struct {
     int64_t n;
-    float rho, trunc_r;
+    float rho, trunc_r, clamp_eps;
     double fmax;                 /* largest |f| */
     uint64_t nonempty_cells;     /* bit c set when cell c holds a primitive */
     int64_t cell_count[12];      /* primitives per cell */
@@ -116,7 +130,7 @@ gf_status gf_mask_cone(gf_scene scene, const float axis[3], float half_angle, ui
 
 /* Deterministic optical depth (Sec. 3, Eq. 2 summed over primitives, each by
  * the closed-form segment integral of Sec. 4.4) and transmittance T = exp(-tau)
- * (Sec. 3, Eq. 3; accumulate-then-exponentiate as in Sec. 4.5 implementation
+ * (Sec. 3, Eq. 3; accumulate-then-exponentiate as in Sec. 4.6 implementation
  * details).  rays: device n x 8; tau: device n (required); T: device n or NULL.
  * image_width: 0 when the rays are an arbitrary list; W > 0 (a multiple of 8
  * dividing n) when they are a row-major image W pixels wide, which lets each
@@ -132,7 +146,8 @@ gf_status gf_optical_depth_counts(gf_scene scene, const float* rays, int64_t n, 
                                   int32_t* nodes, int32_t* hits, void* stream);
 
 /* Point density kappa (Sec. 3, Eq. 1) and the majorant-grid bound kbar at
- * points: pts device n x 3; kappa, kbar device n (kbar may be NULL). */
+ * points: pts device n x 3; kappa, kbar device n (kbar may be NULL; it needs
+ * a scene built with majorant_grid > 0). */
 gf_status gf_density(gf_scene scene, const float* pts, int64_t n, gf_mask mask, float* kappa, float* kbar,
                      void* stream);
 
@@ -149,40 +164,110 @@ gf_status gf_density(gf_scene scene, const float* pts, int64_t n, gf_mask mask, 
 gf_status gf_transmittance_ratio(gf_scene scene, const float* rays, int64_t n, int image_width, gf_mask mask,
                                  int spp, uint64_t seed, float* T_mean, float* T_var, void* stream);
 
+/* Per-segment stochastic mask strategies (Sec. 4.5.1 frequency levels,
+ * Sec. 4.5.2 orientation bins; the two strategy tables of Appendix B).  A
+ * segment draws four uniforms: u0 for its level strategy and u_l for the bin
+ * strategy of each traced level l >= 1 (level 0, the low-pass level, has no
+ * orientation and keeps all its bins).  The result is a weight per cell; a
+ * primitive's density on the segment is multiplied by its cell's weight
+ * (0: not traced).  Every stochastic strategy has expected weight 1 per cell,
+ * so the segment's optical depth is unbiased; the threshold strategies drop
+ * aligned bins deterministically.  P = 4 levels, K = 3 bins,
+ * e = 1 - beta, x = u0^(1/e) a power-law draw:
+ *   GF_LEVEL_ALL            every level, weight 1
+ *   GF_LEVEL_UNIFORM        level floor(P u0), weight P
+ *   GF_LEVEL_POWER          level floor(P x), weight 1 / (b^e - a^e) for its
+ *                           bucket [a, b) = [l/P, (l+1)/P)
+ *   GF_LEVEL_UNIFORM_CV     level 0 weight 1 (control variate) and one of the
+ *                           levels 1..P-1 uniformly, weight P - 1
+ *   GF_LEVEL_POWER_CV       level 0 weight 1 and level 1 + floor((P-1) x),
+ *                           weight 1 / (b^e - a^e) over buckets of width 1/(P-1)
+ *   GF_LEVEL_POWER_CV_ACCUM levels 0..floor(P x), level j with weight
+ *                           1 / (1 - (j/P)^e)
+ * With a_k = |v.e_k| / |v| the alignment of the segment with bin k's axis,
+ * w_k = exp(-m_lk^2 a_k^2 / 2) (m_lk the cell's median |k_W|, k_W = S R^T 2 pi f)
+ * and W = sum_k w_k:
+ *   GF_BIN_ALL              every bin, weight 1
+ *   GF_BIN_THRESHOLD        bins with a_k <= delta, weight 1 (threshold culling)
+ *   GF_BIN_UNIFORM          bin floor(K u_l), weight K
+ *   GF_BIN_IMPORTANCE       bin k with probability w_k / W, weight W / w_k
+ *   GF_BIN_THRESHOLD_UNIFORM bins with a_k <= delta weight 1, plus one of the
+ *                           N others uniformly, weight N
+ *   GF_BIN_MIXTURE          (not in the paper) probability w_k/(2W) + 1/(2K),
+ *                           weight its inverse (at most 2K): importance
+ *                           sampling with bounded weights */
+typedef enum {
+    GF_LEVEL_ALL = 0,
+    GF_LEVEL_UNIFORM = 1,
+    GF_LEVEL_POWER = 2,
+    GF_LEVEL_UNIFORM_CV = 3,
+    GF_LEVEL_POWER_CV = 4,
+    GF_LEVEL_POWER_CV_ACCUM = 5
+} gf_level_strategy;
+
+typedef enum {
+    GF_BIN_ALL = 0,
+    GF_BIN_THRESHOLD = 1,
+    GF_BIN_UNIFORM = 2,
+    GF_BIN_IMPORTANCE = 3,
+    GF_BIN_THRESHOLD_UNIFORM = 4,
+    GF_BIN_MIXTURE = 5
+} gf_bin_strategy;
+
 typedef struct {
-    int spp;            /* camera samples per ray */
+    int spp;            /* camera samples per pixel / ray */
     int multiple;       /* 0: single scattering, 1: multiple scattering */
     int max_scatter;    /* multiple: a collision after this many scatterings ends the path with 0 */
     float albedo;       /* single-scattering albedo */
     float hg_g;         /* Henyey-Greenstein asymmetry (0 = isotropic) */
     float env;          /* constant environment radiance */
-    int stochastic;     /* 1: per-segment stochastic band / orientation mask (Sec. 4.5.1-4.5.2) */
-    gf_mask mask;       /* fixed mask (stochastic == 0) */
+    int stochastic;     /* 1: every segment draws its own cell weights by the two strategies below,
+                           applied on top of `mask` (Sec. 4.5.1-4.5.2) */
+    int level_strategy; /* gf_level_strategy */
+    int bin_strategy;   /* gf_bin_strategy */
+    float beta;         /* power-law shape, 0 <= beta < 1 */
+    float delta;        /* alignment threshold of the threshold strategies, in [0, 1] */
+    int free_flight;    /* 0: weighted delta tracking, transmittances by ratio tracking;
+                           1: CDF inversion of the closed-form optical depth (Sec. 3 and Sec. 4.4),
+                           transmittances exp(-tau) from the closed form */
+    int transmittance;  /* free_flight 0, single scattering: the shadow segment's transmittance by
+                           0 ratio tracking, 1 the closed form exp(-tau) (Sec. 4.4; the tomography case
+                           of Sec. 4.6); same mean, no variance.  free_flight 1 always uses 1. */
+    uint64_t shadow_cells; /* single scattering: cells the shadow rays trace, fixed (Zero-NEE of
+                              Sec. 4.6 implementation details: shadow rays against the low-pass level,
+                              cells 0x7); 0 = the shadow segment's own mask */
+    gf_mask mask;       /* fixed mask; its lod_k applies to camera segments */
     uint64_t seed;
 } gf_render_desc;
 
-/* Radiance per ray with signed-weight delta tracking (free flights) and
- * ratio tracking (shadow ray of single scattering; primary transmittance),
- * both against the per-ray envelope majorant of gf_transmittance_ratio.
- * Single: escape -> w env; real collision -> w albedo T_ratio(x, isotropic
+/* Radiance per ray (Sec. 3 radiative transfer with a constant environment).
+ * Free flights: signed-weight delta tracking against the per-ray envelope
+ * majorant of gf_transmittance_ratio, whose per-cell multipliers are the
+ * cell weights capped at 18 (the estimators stay unbiased for any positive
+ * majorant; weights above the cap only cost variance), with ratio-tracked
+ * transmittances; or (free_flight = 1) the inverse of the cumulative
+ * closed-form optical depth with exact transmittances.
+ * Single: escape -> w env; real collision -> w albedo T(x, isotropic
  * direction) env.  Multiple: free flights with albedo and HG scattering until
- * escape.  Stochastic masks (Sec. 4.5.1-4.5.2, Appendix B tables): each
- * segment keeps level 0 (weight 1) and draws one level l in 1..3 uniformly
- * and one bin k with probability p_k = w_k / (2W) + 1/6 (an even mixture of
- * importance and uniform sampling), w_k = exp(-m_lk^2 a_k^2 / 2),
- * a_k = |v.e_k|, W = sum_k w_k, m_lk = cell median of |k_W|; the drawn cell
- * gets weight 3 / p_k (at most 18).
- * Outputs (device n, variances/T may be NULL): L mean / variance over spp,
- * primary-segment ratio-tracked transmittance mean / variance.
- * image_width as for gf_optical_depth.  Each ray's samples are traced by one
- * lane, so results do not depend on which rays are traced together. */
-gf_status gf_render(gf_scene scene, const float* rays, int64_t n, int image_width, const gf_render_desc* desc,
-                    float* L_mean, float* L_var, float* T_mean, float* T_var, void* stream);
+ * escape; a collision after max_scatter scatterings ends the path with 0.
+ * Outputs (device n, variances / T may be NULL): L mean / variance over spp,
+ * primary-segment transmittance mean / variance.  image_width as for
+ * gf_optical_depth.  Each ray's samples are traced by one lane with random
+ * streams keyed by (seed, ray index, sample), so a ray's result depends on
+ * its index in the launch but not on which rays are traced beside it.  The
+ * call allocates its tracking workspace stream-ordered. */
+gf_status gf_render_rays(gf_scene scene, const float* rays, int64_t n, int image_width, const gf_render_desc* desc,
+                         float* L_mean, float* L_var, float* T_mean, float* T_var, void* stream);
 
-/* Work of gf_render with the same arguments (same random streams):
- * counts[0] tentative collisions, [1] LBVH nodes visited by point queries,
- * [2] primitive records read at leaves, [3] majorant voxels walked.
- * counts: device, 4 x uint64, overwritten.  Used to count algorithmic bytes. */
+/* Work of gf_render_rays with the same arguments (same random streams):
+ * counts[0] tentative collisions, [1] internal LBVH nodes the kernel visited,
+ * [2] primitive records it read at leaves, [3] windows, [4] tentative points
+ * the estimators consume (all of a ratio-tracked segment's, a delta-tracked
+ * one's up to its collision), and for those points [5] the internal nodes a
+ * point query visits (box contains the point, cells pruned) and [6] the
+ * primitives whose truncated support contains the point.  counts: device,
+ * GF_RENDER_COUNTS x uint64, overwritten.  Used to count algorithmic bytes. */
+#define GF_RENDER_COUNTS 7
 gf_status gf_render_counts(gf_scene scene, const float* rays, int64_t n, int image_width, const gf_render_desc* desc,
                            uint64_t* counts, void* stream);
 
@@ -197,7 +282,27 @@ typedef struct {
  * width*height x 8 float32 (t in [0, +inf)). */
 gf_status gf_camera_rays(const gf_camera* cam, float* rays, void* stream);
 
-/* Adjoint of gf_optical_depth (and of T = exp(-tau)): accumulates
+/* Bytes of caller-owned device workspace gf_render needs for this camera and
+ * description (the camera rays plus the tracking lanes' state). */
+gf_status gf_render_workspace_size(gf_scene scene, const gf_camera* cam, const gf_render_desc* desc,
+                                   size_t* bytes);
+
+/* Renders a camera image (the problem statement of Sec. 3: primitives, a
+ * mask and rays in, radiance out), as gf_render_rays over the camera's rays
+ * with the image width as tile width.  workspace: caller-owned device memory
+ * of at least the size gf_render_workspace_size reports (256-byte aligned);
+ * the call allocates nothing.  radiance: device height x width; primary_T:
+ * device height x width or NULL (the camera segment's transmittance
+ * estimate).  GF_EINVAL when ws_bytes is too small. */
+gf_status gf_render(gf_scene scene, const gf_camera* cam, const gf_render_desc* desc, void* workspace,
+                    size_t ws_bytes, float* radiance, float* primary_T, void* stream);
+
+/* Adjoint of gf_optical_depth (and of T = exp(-tau)): the gradient of a
+ * rendered optical-depth / transmittance image with respect to every
+ * primitive parameter, which the regression of Sec. 5 (differentiable
+ * rendering of the kernel mixture) descends; here the closed-form segment
+ * integral of Sec. 4.4 (Appendix A) is differentiated by hand, with the
+ * chord-end (Leibniz) terms of the truncated support.  Accumulates
  * dparams[i*15 + k] = sum_r g_r dtau_r / dparam_{i,k} with
  * g_r = dL_dtau[r] - (dL_dT ? dL_dT[r] * T[r] : 0), by recomputing every
  * segment (no stored paths).  dparams: device n_prims x 15, caller order,

@@ -16,13 +16,13 @@
  *     evaluated with an accurate Faddeeva function;
  *   - extinction field, optical depth and transmittance (Sec. 3, Eqs. 1-3);
  *   - the frequency-level / orientation-bin partition and visibility masks
- *     (Sec. 4.5 implementation details: V_l = 2^l, ray mask AND);
+ *     (Sec. 4.6 implementation details: V_l = 2^l, ray mask AND);
  *   - a Morton-ordered Karras linear BVH over the truncated ellipsoids;
  *   - ratio tracking and weighted delta tracking with local majorants, free
  *     flights by inversion of the cumulative optical depth with a bisection
  *     solver (Sec. 3 CDF inversion; Sec. 4.4 distance sampling), and the
  *     single / multiple scattering estimators built on them, with shadow rays
- *     optionally restricted to chosen cells (Zero-NEE, Sec. 4.5 implementation
+ *     optionally restricted to chosen cells (Zero-NEE, Sec. 4.6 implementation
  *     details);
  *   - the per-segment stochastic band / orientation masks (Sec. 4.5.1-4.5.2,
  *     Appendix B tables): every frequency-level strategy and every
@@ -1091,7 +1091,7 @@ void or_hg_cos(double g, int64_t n, uint64_t seed, double* out)
 
 /* ------------------------------------------------------------------------- */
 /* Per-segment stochastic masks (Sec. 4.5.1 stochastic Laplacian path         */
-/* tracing, Sec. 4.5.2 stochastic orientation-selective path tracing, Sec. 4.5 */
+/* tracing, Sec. 4.5.2 stochastic orientation-selective path tracing, Sec. 4.6 */
 /* implementation steps 1-5; Appendix B tables of frequency-level and         */
 /* orientation-bin strategies).  P = 4 levels (level 0 the low-pass level),   */
 /* K = 3 orientation bins with representative directions o_k = e_k.  A       */
@@ -1279,7 +1279,7 @@ static void draw_segment_weights(const int32_t* cell, const double* wfix, int64_
  * on escape it returns w L_env; on a real collision w albedo T(x, w_iso) L_env
  * with w_iso uniform on the sphere (a shadow ray toward the constant
  * environment; with shadow cells != 0 it is traced against those cells only:
- * the Zero-NEE strategy of Sec. 4.5 implementation details traces shadow rays
+ * the Zero-NEE strategy of Sec. 4.6 implementation details traces shadow rays
  * against the low-pass level).  Multiple scattering: repeat free flights,
  * albedo and HG per collision, terminate with 0 when a collision happens
  * after max_scatter scatterings.

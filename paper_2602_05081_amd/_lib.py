@@ -26,15 +26,16 @@ class GfError(RuntimeError):
 
 
 class gf_mask(C.Structure):
-    _fields_ = [("cells", C.c_uint64), ("prim_bits", C.c_void_p)]
+    _fields_ = [("cells", C.c_uint64), ("prim_bits", C.c_void_p), ("lod_k", C.c_float)]
 
 
 class gf_scene_desc(C.Structure):
-    _fields_ = [("rho", C.c_float), ("trunc_r", C.c_float), ("majorant_grid", C.c_int)]
+    _fields_ = [("rho", C.c_float), ("trunc_r", C.c_float), ("majorant_grid", C.c_int), ("clamp_eps", C.c_float)]
 
 
 class gf_scene_info_t(C.Structure):
-    _fields_ = [("n", C.c_int64), ("rho", C.c_float), ("trunc_r", C.c_float), ("fmax", C.c_double),
+    _fields_ = [("n", C.c_int64), ("rho", C.c_float), ("trunc_r", C.c_float), ("clamp_eps", C.c_float),
+                ("fmax", C.c_double),
                 ("nonempty_cells", C.c_uint64), ("cell_count", C.c_int64 * 12),
                 ("cell_median_kw", C.c_float * 12), ("grid_res", C.c_int), ("bounds_lo", C.c_float * 3),
                 ("bounds_hi", C.c_float * 3), ("device_bytes", C.c_size_t)]
@@ -42,8 +43,14 @@ class gf_scene_info_t(C.Structure):
 
 class gf_render_desc(C.Structure):
     _fields_ = [("spp", C.c_int), ("multiple", C.c_int), ("max_scatter", C.c_int), ("albedo", C.c_float),
-                ("hg_g", C.c_float), ("env", C.c_float), ("stochastic", C.c_int), ("mask", gf_mask),
-                ("seed", C.c_uint64)]
+                ("hg_g", C.c_float), ("env", C.c_float), ("stochastic", C.c_int), ("level_strategy", C.c_int),
+                ("bin_strategy", C.c_int), ("beta", C.c_float), ("delta", C.c_float), ("free_flight", C.c_int),
+                ("transmittance", C.c_int), ("shadow_cells", C.c_uint64), ("mask", gf_mask), ("seed", C.c_uint64)]
+
+
+# strategy codes of the per-segment stochastic masks (gf_level_strategy / gf_bin_strategy)
+LEVEL = dict(deterministic=0, uniform=1, power=2, uniform_cv=3, power_cv=4, power_cv_accum=5)
+BIN = dict(deterministic=0, threshold=1, uniform=2, importance=3, threshold_uniform=4, mixture=5)
 
 
 class gf_camera(C.Structure):
@@ -69,7 +76,9 @@ _SIGS = {
     "gf_optical_depth_counts": [_vp, _vp, _i64, _i, gf_mask, _vp, _vp, _vp],
     "gf_density": [_vp, _vp, _i64, gf_mask, _vp, _vp, _vp],
     "gf_transmittance_ratio": [_vp, _vp, _i64, _i, gf_mask, _i, _u64, _vp, _vp, _vp],
-    "gf_render": [_vp, _vp, _i64, _i, C.POINTER(gf_render_desc), _vp, _vp, _vp, _vp, _vp],
+    "gf_render_rays": [_vp, _vp, _i64, _i, C.POINTER(gf_render_desc), _vp, _vp, _vp, _vp, _vp],
+    "gf_render_workspace_size": [_vp, C.POINTER(gf_camera), C.POINTER(gf_render_desc), C.POINTER(C.c_size_t)],
+    "gf_render": [_vp, C.POINTER(gf_camera), C.POINTER(gf_render_desc), _vp, C.c_size_t, _vp, _vp, _vp],
     "gf_render_counts": [_vp, _vp, _i64, _i, C.POINTER(gf_render_desc), _vp, _vp],
     "gf_camera_rays": [C.POINTER(gf_camera), _vp, _vp],
     "gf_optical_depth_backward": [_vp, _vp, _i64, _i, gf_mask, _vp, _vp, _vp, _vp, _vp],
@@ -130,16 +139,17 @@ def _ptr(t, dtype=None, optional=False):
     return C.c_void_p(t.data_ptr())
 
 
-def make_mask(cells=FULL_CELLS, prim_bits=None) -> gf_mask:
-    return gf_mask(cells, None if prim_bits is None else prim_bits.data_ptr())
+def make_mask(cells=FULL_CELLS, prim_bits=None, lod_k=0.0) -> gf_mask:
+    return gf_mask(cells, None if prim_bits is None else prim_bits.data_ptr(), lod_k)
 
 
 class Scene:
     """A resident scene (owns the C handle)."""
 
-    def __init__(self, params: torch.Tensor, rho: float, trunc_r: float = 3.0, majorant_grid: int = 64):
+    def __init__(self, params: torch.Tensor, rho: float, trunc_r: float = 3.0, majorant_grid: int = 0,
+                 clamp_eps: float = 0.0):
         h = C.c_void_p()
-        desc = gf_scene_desc(rho, trunc_r, majorant_grid)
+        desc = gf_scene_desc(rho, trunc_r, majorant_grid, clamp_eps)
         _check(lib().gf_scene_create(_ptr(params, torch.float32), params.shape[0], C.byref(desc), _stream(),
                                      C.byref(h)))
         self.handle = h
@@ -162,8 +172,8 @@ class Scene:
             pass
 
 
-def gf_scene_create(params, rho, trunc_r=3.0, majorant_grid=64) -> Scene:
-    return Scene(params, rho, trunc_r, majorant_grid)
+def gf_scene_create(params, rho, trunc_r=3.0, majorant_grid=0, clamp_eps=0.0) -> Scene:
+    return Scene(params, rho, trunc_r, majorant_grid, clamp_eps)
 
 
 def gf_scene_export_lbvh(scene: Scene):
@@ -242,24 +252,54 @@ def gf_transmittance_ratio(scene: Scene, rays, spp, seed, mask: gf_mask = None, 
 
 
 def render_desc(spp=1, multiple=False, max_scatter=16, albedo=0.9, hg_g=0.0, env=1.0, stochastic=False,
-                mask: gf_mask = None, seed=0) -> gf_render_desc:
-    return gf_render_desc(spp, int(multiple), max_scatter, albedo, hg_g, env, int(stochastic),
-                          mask if mask is not None else make_mask(), seed)
+                mask: gf_mask = None, seed=0, level="uniform_cv", bin="importance", beta=0.0, delta=1.0,
+                analytic=False, exact_shadow=False, shadow_cells=0) -> gf_render_desc:
+    """level / bin: strategy names (LEVEL, BIN) or codes; analytic: free
+    flights by CDF inversion with exact transmittances; exact_shadow:
+    closed-form shadow transmittance with delta-tracked free flights;
+    shadow_cells: cells the single-scattering shadow rays trace (0: their
+    own mask)."""
+    lv = LEVEL[level] if isinstance(level, str) else int(level)
+    bn = BIN[bin] if isinstance(bin, str) else int(bin)
+    return gf_render_desc(spp, int(multiple), max_scatter, albedo, hg_g, env, int(stochastic), lv, bn, beta, delta,
+                          int(analytic), int(exact_shadow), shadow_cells, mask if mask is not None else make_mask(),
+                          seed)
 
 
-def gf_render(scene: Scene, rays, desc: gf_render_desc, image_width=0, want_var=True):
+def gf_render_rays(scene: Scene, rays, desc: gf_render_desc, image_width=0, want_var=True):
     n = rays.shape[0]
     f = lambda: torch.empty(n, dtype=torch.float32, device=rays.device)  # noqa: E731
     Lm, Tm = f(), f()
     Lv, Tv = (f(), f()) if want_var else (None, None)
-    _check(lib().gf_render(scene.handle, _ptr(rays, torch.float32), n, image_width, C.byref(desc), _ptr(Lm),
-                           _ptr(Lv, optional=True), _ptr(Tm), _ptr(Tv, optional=True), _stream()))
+    _check(lib().gf_render_rays(scene.handle, _ptr(rays, torch.float32), n, image_width, C.byref(desc), _ptr(Lm),
+                                _ptr(Lv, optional=True), _ptr(Tm), _ptr(Tv, optional=True), _stream()))
     return Lm, Lv, Tm, Tv
 
 
+def gf_render_workspace_size(scene: Scene, cam, desc: gf_render_desc) -> int:
+    out = C.c_size_t()
+    _check(lib().gf_render_workspace_size(scene.handle, C.byref(cam), C.byref(desc), C.byref(out)))
+    return out.value
+
+
+def gf_render(scene: Scene, cam, desc: gf_render_desc, workspace: torch.Tensor, want_T=True):
+    """Camera image (height x width radiance, and the primary transmittance)
+    rendered in a caller-owned workspace (a uint8 device tensor of at least
+    gf_render_workspace_size bytes)."""
+    rad = torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda")
+    T = torch.empty_like(rad) if want_T else None
+    _check(lib().gf_render(scene.handle, C.byref(cam), C.byref(desc), _ptr(workspace), workspace.numel(),
+                           _ptr(rad), _ptr(T, optional=True), _stream()))
+    return rad, T
+
+
+GF_RENDER_COUNTS = 7
+
+
 def gf_render_counts(scene: Scene, rays, desc: gf_render_desc, image_width=0):
-    """(tentative collisions, point-query nodes, primitive records, voxels)"""
-    out = torch.zeros(4, dtype=torch.int64, device=rays.device)
+    """(tentative points, nodes visited, primitive records read, windows,
+    points consumed, their point-query nodes, their covering primitives)"""
+    out = torch.zeros(GF_RENDER_COUNTS, dtype=torch.int64, device=rays.device)
     _check(lib().gf_render_counts(scene.handle, _ptr(rays, torch.float32), rays.shape[0], image_width,
                                   C.byref(desc), _ptr(out), _stream()))
     return [int(x) for x in out.cpu()]

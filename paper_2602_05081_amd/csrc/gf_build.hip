@@ -326,7 +326,27 @@ __global__ __launch_bounds__(256) void k_karras(const uint64_t* __restrict__ key
 // ---------------------------------------------------------------------------
 // 5. Morton-ordered primitive records and leaf boxes
 // ---------------------------------------------------------------------------
+// Adaptive clamping (Sec. 4.4): the truncation radius of a primitive whose
+// kernel magnitude rho |alpha| (2 pi)^-3/2 / (s0 s1 s2) exp(-E^2/2), taken on
+// the ray of largest chord measure (times s_max / sqrt(2 pi) for the
+// integral across it), drops below eps at Mahalanobis radius E:
+// E^2 = 2 ln(rho |alpha| s_max / (2 pi s0 s1 s2 eps)); the radius is
+// min(r, E), 0 when E^2 <= 0.  The paper's own extent drops alpha and the
+// Jacobian and subtracts |k_W|^2, which no ray perpendicular to k_W
+// attains, so it is no bound; the carrier is left out here.  eps = 0: r.
+static __device__ double clamp_radius(const float* p, double r, double rho, double eps) {
+#pragma clang fp contract(off)
+    if (!(eps > 0.0)) return r;
+    double s0 = p[7], s1 = p[8], s2 = p[9];
+    double smax = fmax(s0, fmax(s1, s2));
+    double arg = rho * fabs((double)p[14]) * smax / (2.0 * GF_PI * s0 * s1 * s2 * eps);
+    if (!(arg > 1.0)) return 0.0;
+    double E = sqrt(2.0 * log(arg));
+    return E < r ? E : r;
+}
+
 __global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ params, int n, float r, float rho,
+                                                float clamp_eps,
                                                 const BoundsPartial* __restrict__ bnd, const uint32_t* __restrict__ perm,
                                                 float4* __restrict__ prims, float* __restrict__ aabb,
                                                 uint64_t* __restrict__ cellor, float* __restrict__ kw,
@@ -339,11 +359,12 @@ __global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ params
     rotation64(p, R, qh);
     double s[3] = {p[7], p[8], p[9]};
     float* bx = aabb + (size_t)(n - 1 + j) * 6;
+    const double rr = clamp_radius(p, (double)r, (double)rho, (double)clamp_eps);
     {
 #pragma clang fp contract(off)
         for (int a = 0; a < 3; ++a) {
             double t0 = R[a][0] * s[0], t1 = R[a][1] * s[1], t2 = R[a][2] * s[2];
-            double e = (double)r * sqrt((t0 * t0 + t1 * t1) + t2 * t2);
+            double e = rr * sqrt((t0 * t0 + t1 * t1) + t2 * t2);
             bx[a] = __double2float_rd((double)p[a] - e);
             bx[3 + a] = __double2float_ru((double)p[a] + e);
         }
@@ -364,7 +385,7 @@ __global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ params
     rec[0] = make_float4(p[0], p[1], p[2], p[13]);
     rec[1] = make_float4((float)A[0], (float)A[1], (float)A[2], (float)A[3]);
     rec[2] = make_float4((float)A[4], (float)A[5], p[10], p[11]);
-    rec[3] = make_float4(p[12], (float)amp, __int_as_float(cell), __int_as_float(i));
+    rec[3] = make_float4(p[12], (float)amp, (float)(rr * rr), rec_word(i, cell));
     double qn = sqrt(((double)p[3] * p[3] + (double)p[4] * p[4]) + (double)p[5] * p[5] + (double)p[6] * p[6]);
     float4* ax = aux + (size_t)j * 3;
     ax[0] = make_float4(p[3], p[4], p[5], p[6]);
@@ -533,7 +554,7 @@ __global__ __launch_bounds__(256) void k_grid_final(const unsigned long long* __
 __global__ __launch_bounds__(256) void k_cells_morton(const float4* __restrict__ prims, int n,
                                                       int32_t* __restrict__ out) {
     int j = blockIdx.x * 256 + threadIdx.x;
-    if (j < n) out[j] = __float_as_int(prims[(size_t)j * 4 + 3].z);
+    if (j < n) out[j] = rec_cell(prims[(size_t)j * 4 + 3].w);
 }
 
 __global__ __launch_bounds__(256) void k_cells_export(const float4* __restrict__ prims, int n,
@@ -541,7 +562,7 @@ __global__ __launch_bounds__(256) void k_cells_export(const float4* __restrict__
     int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     float4 r = prims[(size_t)j * 4 + 3];
-    out[__float_as_int(r.w)] = __float_as_int(r.z);
+    out[rec_orig(r.w)] = rec_cell(r.w);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,8 +608,10 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     if (!(desc->rho > 0.0f) || !isfinite(desc->rho)) return gf_fail(GF_EINVAL, "gf_scene_create: rho must be > 0");
     float r = desc->trunc_r == 0.0f ? 3.0f : desc->trunc_r;
     if (!(r > 0.0f) || !isfinite(r)) return gf_fail(GF_EINVAL, "gf_scene_create: trunc_r must be > 0");
-    int G = desc->majorant_grid == 0 ? 64 : desc->majorant_grid;
-    if (G < 1 || G > 512) return gf_fail(GF_EINVAL, "gf_scene_create: majorant_grid must be in [1, 512]");
+    if (!(desc->clamp_eps >= 0.0f) || !isfinite(desc->clamp_eps))
+        return gf_fail(GF_EINVAL, "gf_scene_create: clamp_eps must be finite and >= 0");
+    int G = desc->majorant_grid;
+    if (G < 0 || G > 512) return gf_fail(GF_EINVAL, "gf_scene_create: majorant_grid must be in [0, 512]");
     gf_status st = gf_ensure_weideman_tau();
     if (st != GF_OK) return st;
     st = gf_ensure_weideman_grad();
@@ -602,6 +625,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     s->n = n;
     s->rho = desc->rho;
     s->r = r;
+    s->clamp_eps = desc->clamp_eps;
     s->G = G;
     size_t total = 0;
     GF_TRY(dalloc(&s->prims, (size_t)n * 4, &total));
@@ -651,7 +675,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     GF_STRY(dalloc(&hist, (size_t)ntiles * RS_DIGITS, &scratch_bytes));
     GF_STRY(dalloc(&visits, std::max<int64_t>(n - 1, 1), &scratch_bytes));
     GF_STRY(dalloc(&kw, n, &scratch_bytes));
-    GF_STRY(dalloc(&gacc, (size_t)G * G * G * GF_NCELLS, &scratch_bytes));
+    if (G > 0) GF_STRY(dalloc(&gacc, (size_t)G * G * G * GF_NCELLS, &scratch_bytes));
     GF_STRY(dalloc(&ranges, std::max<int64_t>(n - 1, 1), &scratch_bytes));
 
     // 1. validation, bounds, |f| max
@@ -690,7 +714,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
                 ? GF_OK : gf_hip_check(hipGetLastError(), "memset"));
     if (n > 1) k_karras<<<nblk(n - 1), 256, 0, sm>>>(s->keys, ni, s->left, s->right, s->parent, ranges);
     // 5. records and leaves
-    k_leaves<<<nblk(n), 256, 0, sm>>>(params, ni, r, s->rho, parts, (const uint32_t*)s->perm, s->prims, s->aabb,
+    k_leaves<<<nblk(n), 256, 0, sm>>>(params, ni, r, s->rho, s->clamp_eps, parts, (const uint32_t*)s->perm, s->prims, s->aabb,
                                       s->cellor, kw, s->aux, s->A64);
     // 6-7. refit and traversal records
     if (n > 1) {
@@ -740,11 +764,17 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
             s->med[c] = per[c][m];
         }
     }
-    // 8. majorant grid over the root box
+    // 8. scene box; majorant grid over it (optional)
     for (int a = 0; a < 3; ++a) {
         s->lo[a] = root[a];
         s->hi[a] = root[3 + a];
         if (!(s->hi[a] > s->lo[a])) s->hi[a] = s->lo[a] + 1e-6f;
+    }
+    if (G == 0) {
+        GF_STRY(hipStreamSynchronize(sm) == hipSuccess ? GF_OK : gf_hip_check(hipGetLastError(), "sync"));
+        cleanup();
+        *out = s;
+        return GF_OK;
     }
     float3 glo = make_float3(s->lo[0], s->lo[1], s->lo[2]);
     float3 gh = make_float3((s->hi[0] - s->lo[0]) / G, (s->hi[1] - s->lo[1]) / G, (s->hi[2] - s->lo[2]) / G);
@@ -772,6 +802,7 @@ extern "C" gf_status gf_scene_info(gf_scene s, gf_scene_info_t* info) {
     info->n = s->n;
     info->rho = s->rho;
     info->trunc_r = s->r;
+    info->clamp_eps = s->clamp_eps;
     info->fmax = sqrt(s->fmax2);
     info->nonempty_cells = s->nonempty;
     for (int c = 0; c < GF_NCELLS; ++c) {
@@ -831,7 +862,7 @@ __global__ __launch_bounds__(256) void k_cone_rec(const float4* __restrict__ pri
 #pragma clang fp contract(off)
         f2 = (fx * fx + fy * fy) + fz * fz;
     }
-    int orig = __float_as_int(r3.w);
+    int orig = rec_orig(r3.w);
     if (fa * fa <= c2 * f2) atomicOr(&bits[orig >> 5], 1u << (orig & 31));
 }
 
@@ -842,7 +873,8 @@ extern "C" gf_status gf_mask_cone(gf_scene s, const float axis[3], float half_an
     if (!(an > 0.0) || !isfinite(an) || !isfinite(half_angle))
         return gf_fail(GF_EINVAL, "gf_mask_cone: invalid axis or angle");
     hipStream_t sm = (hipStream_t)stream;
-    GF_HIP(hipMemsetAsync(prim_bits, 0, sizeof(uint32_t) * ((s->n + 31) / 32), sm));
+    gf_status st = gf_zero_words(prim_bits, (size_t)((s->n + 31) / 32), sm);
+    if (st != GF_OK) return st;
     double c = cos((double)half_angle);
     k_cone_rec<<<nblk(s->n), 256, 0, sm>>>(s->prims, (int)s->n, axis[0] / an, axis[1] / an, axis[2] / an, c * c,
                                            prim_bits);
@@ -872,9 +904,20 @@ SceneView gf_scene_view(const gf_scene_s* s) {
     return v;
 }
 
-gf_status gf_check_mask(const gf_scene_s* s, const gf_mask& m) {
-    (void)s;
-    (void)m;
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* __restrict__ p, size_t words) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
+gf_status gf_zero_words(void* p, size_t words, hipStream_t sm) {
+    if (words == 0) return GF_OK;
+    size_t blocks = (words + 255) / 256;
+    k_zero_words<<<(unsigned)(blocks < 4096 ? blocks : 4096), 256, 0, sm>>>((uint32_t*)p, words);
+    GF_HIP(hipGetLastError());
+    return GF_OK;
+}
+
+gf_status gf_check_mask(const gf_mask& m, const char* who) {
+    if (!(m.lod_k >= 0.0f) || !isfinite(m.lod_k)) return gf_fail(GF_EINVAL, "%s: mask lod_k must be finite and >= 0", who);
     return GF_OK;
 }
 
@@ -882,5 +925,7 @@ MaskView gf_mask_view(const gf_mask& m) {
     MaskView v;
     v.cells = (uint32_t)(m.cells & 0xfffu);
     v.prim_bits = m.prim_bits;
+    v.lod_k = m.lod_k > 0.0f ? m.lod_k : 0.0f;
+    v.lod2 = v.lod_k * v.lod_k;
     return v;
 }

@@ -223,8 +223,8 @@ __global__ __launch_bounds__(256) void k_tau_bwd(SceneView S, MaskView M, const 
 #pragma unroll
         for (int k = 0; k < 15; ++k) g[k] = 0.0f;
         HitGeom H;
-        bool hit = active && hit_geom(P, R, S.r2, S.A64 + (size_t)j * 6, H);
-        if (hit) hit_grad(P, S.aux + (size_t)j * 3, H, R, S.r2, gr, g);
+        bool hit = active && hit_geom(P, R, P.r2, S.A64 + (size_t)j * 6, H) && lod_keep64(P, R, H, M.lod_k);
+        if (hit) hit_grad(P, S.aux + (size_t)j * 3, H, R, P.r2, gr, g);
         if (!__ballot(hit)) return;
         float* dst = dparams + (size_t)P.orig * 15;
 #pragma unroll
@@ -242,11 +242,12 @@ extern "C" gf_status gf_optical_depth_backward(gf_scene s, const float* rays, in
         return gf_fail(GF_EINVAL, "gf_optical_depth_backward: NULL argument");
     if ((dL_dT == nullptr) != (T == nullptr))
         return gf_fail(GF_EINVAL, "gf_optical_depth_backward: dL_dT and T must be both given or both NULL");
-    gf_status st = gf_check_rays(n, image_width, "gf_optical_depth_backward");
-    if (st != GF_OK) return st;
     hipStream_t sm = (hipStream_t)stream;
-    GF_HIP(hipMemsetAsync(dparams, 0, sizeof(float) * 15 * (size_t)s->n, sm));
-    if (n == 0) return GF_OK;
+    gf_status st = gf_check_rays(n, image_width, "gf_optical_depth_backward");
+    if (st == GF_OK) st = gf_check_mask(mask, "gf_optical_depth_backward");
+    if (st == GF_OK && n > 0) st = gf_validate_rays(rays, n, sm, "gf_optical_depth_backward");
+    if (st == GF_OK) st = gf_zero_words(dparams, 15 * (size_t)s->n, sm);
+    if (st != GF_OK || n == 0) return st;
     k_tau_bwd<<<gf_packet_blocks(n, image_width), 256, 0, sm>>>(gf_scene_view(s), gf_mask_view(mask), rays, (int)n,
                                                                image_width, dL_dtau, dL_dT, T, dparams);
     GF_HIP(hipGetLastError());

@@ -76,6 +76,7 @@ struct PrimF {
     float mux, muy, muz, phi;
     float a00, a01, a02, a11, a12, a22;
     float fx, fy, fz, amp;
+    float r2;  // square of the truncation radius
     int cell, orig;
 };
 
@@ -86,7 +87,7 @@ static __device__ __forceinline__ PrimF load_prim(const float4* __restrict__ pri
     p.mux = r0.x; p.muy = r0.y; p.muz = r0.z; p.phi = r0.w;
     p.a00 = r1.x; p.a01 = r1.y; p.a02 = r1.z; p.a11 = r1.w;
     p.a12 = r2.x; p.a22 = r2.y; p.fx = r2.z; p.fy = r2.w;
-    p.fz = r3.x; p.amp = r3.y; p.cell = __float_as_int(r3.z); p.orig = __float_as_int(r3.w);
+    p.fz = r3.x; p.amp = r3.y; p.r2 = r3.z; p.cell = rec_cell(r3.w); p.orig = rec_orig(r3.w);
     return p;
 }
 
@@ -170,6 +171,18 @@ static __device__ __forceinline__ bool hit_geom(const PrimF& P, const RayD& R, f
                                                 const double* __restrict__ A64j, HitGeom& H) {
     double A[6] = {A64j[0], A64j[1], A64j[2], A64j[3], A64j[4], A64j[5]};
     return hit_geom_a(P, R, r2, A, true, H) == 1;
+}
+
+// Continuous LOD in binary64 (supplementary "LOD Selection"): primitive P
+// stays on ray R unless its closest point lies ahead of the origin, at the
+// distance d = tc |v|, with |f| d > lod_k (0: no cutoff).  The cutoff itself
+// is held fixed by the adjoint.
+static __device__ __forceinline__ bool lod_keep64(const PrimF& P, const RayD& R, const HitGeom& H, float lod_k) {
+#pragma clang fp contract(off)
+    if (!(lod_k > 0.0f) || !(H.tc > 0.0)) return true;
+    double f2 = ((double)P.fx * P.fx + (double)P.fy * P.fy) + (double)P.fz * P.fz;
+    double v2 = R.vx * R.vx + R.vy * R.vy + R.vz * R.vz;
+    return f2 * (H.tc * H.tc * v2) <= (double)lod_k * (double)lod_k;
 }
 
 // Gauss-Legendre, 8 nodes on [-1, 1] (positive half; the rule is symmetric)

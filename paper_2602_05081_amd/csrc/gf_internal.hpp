@@ -4,8 +4,10 @@
 //   prims  : n x 64 B records (4 x float4), read wave-uniformly through the
 //            scalar cache by the packet traversal:
 //            [mu.x mu.y mu.z phi] [A00 A01 A02 A11] [A12 A22 f.x f.y]
-//            [f.z amp cell orig]  with A = Sigma^-1 (float32), amp = rho alpha /
-//            (4 pi s0 s1 s2), cell = 3 level + bin, orig = caller index.
+//            [f.z amp r^2 (orig | cell << 28)]  with A = Sigma^-1 (float32),
+//            amp = rho alpha / (4 pi s0 s1 s2), r the primitive's truncation
+//            radius (the scene's, or less under adaptive clamping), cell =
+//            3 level + bin, orig = caller index (< 2^28).
 //   nodes  : (n-1) x 64 B traversal records of the internal LBVH nodes, each
 //            holding both child boxes so one scalar load tests both children:
 //            [lbox lo/hi] [rbox lo/hi] [lchild rchild cells pad]; a child id
@@ -30,6 +32,13 @@
 #define GF_NCELLS 12
 #define GF_STACK 128
 #define GF_LEAF_MAX 4
+
+// last word of a primitive record: caller index in the low 28 bits, cell above
+static __device__ __forceinline__ int rec_orig(float w) { return __float_as_int(w) & 0x0FFFFFFF; }
+static __device__ __forceinline__ int rec_cell(float w) { return (int)((unsigned)__float_as_int(w) >> 28); }
+static __device__ __forceinline__ float rec_word(int orig, int cell) {
+    return __int_as_float((int)((unsigned)orig | ((unsigned)cell << 28)));
+}
 
 // Leaf range of a collapsed child id c < 0.
 static __device__ __forceinline__ void leaf_range(int c, int* first, int* count) {
@@ -66,12 +75,14 @@ struct SceneView {
 struct MaskView {
     uint32_t cells;                          // 12 used bits
     const uint32_t* __restrict__ prim_bits;  // caller order, may be null
+    float lod_k;                             // continuous-LOD cutoff (0: off)
+    float lod2;                              // its square
 };
 
 struct gf_scene_s {
     int device;
     int64_t n;
-    float rho, r;
+    float rho, r, clamp_eps;
     int G;
     int depth;  // largest number of internal nodes on a root-to-leaf path
     double fmax2;
@@ -117,7 +128,32 @@ SceneView gf_scene_view(const gf_scene_s* s);
 unsigned gf_packet_blocks(int64_t n, int tile_w);
 gf_status gf_check_rays(int64_t n, int tile_w, const char* who);
 MaskView gf_mask_view(const gf_mask& m);
-gf_status gf_check_mask(const gf_scene_s* s, const gf_mask& m);
+gf_status gf_check_mask(const gf_mask& m, const char* who);
+// Rejects (GF_EINVAL) rays with a NaN/Inf origin, direction or tmin, a NaN
+// tmax, |v| = 0 or tmin > tmax: one check kernel on `sm`, whose verdict the
+// call waits for, before any compute kernel is launched.
+gf_status gf_validate_rays(const float* rays, int64_t n, hipStream_t sm, const char* who);
+
+// Zeroes `words` 32-bit words with a fill kernel on `sm` (a kernel rather
+// than a memset node, so the call can sit in a captured HIP graph).
+gf_status gf_zero_words(void* p, size_t words, hipStream_t sm);
+
+// Tracking workspace of the render kernels: a head of GF_TRACK_HEAD_FLOATS
+// floats (the launch's chunk counter), then GF_TRACK_WAVE_FLOATS floats per
+// resident wave.
+#define GF_TRACK_HEAD_FLOATS 64
+#define GF_TRACK_WAVE_FLOATS (256 * 64)
+
+// host helpers of the render and serving code (gf_track.hip)
+gf_status gf_check_track_depth(const gf_scene_s* s, const char* who);
+// render of n rays with the tracking workspace ws (head + at least
+// min(max_waves, chunks) slices); outputs as gf_render
+gf_status gf_render_launch_in(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
+                              float* ws, float* radiance, float* primary_T, hipStream_t sm, unsigned max_waves);
+gf_status gf_camera_launch(const gf_camera* cam, float* rays, hipStream_t sm);
+gf_status gf_check_camera(const gf_camera* cam, const char* who);
+gf_status gf_check_render_desc(const gf_render_desc* d, const char* who);
+gf_status gf_ensure_weideman_track();
 
 // ---------------------------------------------------------------------------
 // device helpers

@@ -24,9 +24,6 @@
 #include "gf_internal.hpp"
 #include "gf_sched.hpp"
 
-gf_status gf_camera_launch(const gf_camera* cam, float* rays, hipStream_t sm);
-gf_status gf_check_camera(const gf_camera* cam, const char* who);
-gf_status gf_check_render_desc(const gf_render_desc* d, const char* who);
 gf_status gf_serve_fill_req(const gf_request* q, const float* rays, void* out_desc);
 size_t gf_serve_req_size();
 size_t gf_serve_tile_size();
@@ -136,6 +133,8 @@ extern "C" gf_status gf_server_submit(gf_server S, const gf_request* q, uint64_t
     gf_status st = gf_check_camera(&q->camera, "gf_server_submit");
     if (st == GF_OK) st = gf_check_render_desc(&q->render, "gf_server_submit");
     if (st != GF_OK) return st;
+    if (q->render.free_flight != 0)
+        return gf_fail(GF_EINVAL, "gf_server_submit: the server batches delta-tracked renders only (free_flight 0)");
     if (q->scene->depth > 64) return gf_fail(GF_EINVAL, "gf_server_submit: scene LBVH deeper than 64");
     size_t bytes = gfs::request_bytes(q->camera.width, q->camera.height);
     if (bytes > S->mem.budget)

@@ -7,11 +7,13 @@
 // are shared by all 64 rays; each lane tests its own ray against both child
 // boxes and the wave descends where any lane hits (ballot).  A subtree whose
 // cell mask misses the query mask is skipped before its boxes are tested
-// (visibility masks of Sec. 4.5, implementation details).  Per-ray sums are
+// (visibility masks of Sec. 4.6, implementation details).  Per-ray sums are
 // binary64; the summation order is the depth-first leaf order, independent of
 // which other rays share the wave.
 #include <math.h>
 #include <string.h>
+
+#include <atomic>
 
 #include "gf_hit.hpp"
 
@@ -88,7 +90,8 @@ __global__ __launch_bounds__(256) void k_tau(SceneView S, MaskView M, const floa
         if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
         if (!active) return;
         HitGeom H;
-        if (!hit_geom(P, R, S.r2, S.A64 + (size_t)j * 6, H)) return;
+        if (!hit_geom(P, R, P.r2, S.A64 + (size_t)j * 6, H)) return;
+        if (!lod_keep64(P, R, H, M.lod_k)) return;
         if (COUNT) ++nh;
         else acc += (double)hit_value(P, H, c_weid, c_weidL, c_weid64, c_weidL64);
     });
@@ -118,10 +121,50 @@ gf_status gf_check_rays(int64_t n, int tile_w, const char* who) {
     return GF_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Validation of caller rays.  One slot of g_bad_ray per call (taken round
+// robin, so concurrent calls on different streams do not share one)
+// receives the smallest index of an invalid ray; the host waits for it.
+// ---------------------------------------------------------------------------
+#define RAY_CHECK_SLOTS 64
+static __device__ unsigned g_bad_ray[RAY_CHECK_SLOTS];
+
+__global__ __launch_bounds__(256) void k_check_rays(const float* __restrict__ rays, int n, unsigned* __restrict__ bad) {
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float* r = rays + (size_t)i * 8;
+    bool ok = true;
+    for (int a = 0; a < 7; ++a) ok = ok && isfinite(r[a]);
+    ok = ok && !isnan(r[7]) && r[6] <= r[7];
+    ok = ok && (r[3] != 0.0f || r[4] != 0.0f || r[5] != 0.0f);
+    if (!ok) atomicMin(bad, (unsigned)i);
+}
+
+__global__ void k_set_word(unsigned* p, unsigned v) { *p = v; }
+
+gf_status gf_validate_rays(const float* rays, int64_t n, hipStream_t sm, const char* who) {
+    static std::atomic<unsigned> next_slot{0};
+    if (n <= 0) return GF_OK;
+    unsigned* slots = nullptr;
+    GF_HIP(hipGetSymbolAddress((void**)&slots, HIP_SYMBOL(g_bad_ray)));
+    unsigned* bad = slots + (next_slot.fetch_add(1) % RAY_CHECK_SLOTS);
+    k_set_word<<<1, 1, 0, sm>>>(bad, 0xFFFFFFFFu);
+    k_check_rays<<<(unsigned)((n + 255) / 256), 256, 0, sm>>>(rays, (int)n, bad);
+    GF_HIP(hipGetLastError());
+    unsigned first = 0;
+    GF_HIP(hipMemcpyAsync(&first, bad, sizeof(first), hipMemcpyDeviceToHost, sm));
+    GF_HIP(hipStreamSynchronize(sm));
+    if (first != 0xFFFFFFFFu)
+        return gf_fail(GF_EINVAL, "%s: ray %u is invalid (NaN/Inf, |v| = 0 or tmin > tmax)", who, first);
+    return GF_OK;
+}
+
 extern "C" gf_status gf_optical_depth(gf_scene s, const float* rays, int64_t n, int image_width, gf_mask mask,
                                       float* tau, float* T, void* stream) {
     if (!s || (!rays && n) || (!tau && n)) return gf_fail(GF_EINVAL, "gf_optical_depth: NULL argument");
     gf_status st = gf_check_rays(n, image_width, "gf_optical_depth");
+    if (st == GF_OK) st = gf_check_mask(mask, "gf_optical_depth");
+    if (st == GF_OK && n > 0) st = gf_validate_rays(rays, n, (hipStream_t)stream, "gf_optical_depth");
     if (st != GF_OK) return st;
     if (n == 0) return GF_OK;
     unsigned nb = gf_packet_blocks(n, image_width);
@@ -135,6 +178,8 @@ extern "C" gf_status gf_optical_depth_counts(gf_scene s, const float* rays, int6
                                              gf_mask mask, int32_t* nodes, int32_t* hits, void* stream) {
     if (!s || (!rays && n)) return gf_fail(GF_EINVAL, "gf_optical_depth_counts: NULL argument");
     gf_status st = gf_check_rays(n, image_width, "gf_optical_depth_counts");
+    if (st == GF_OK) st = gf_check_mask(mask, "gf_optical_depth_counts");
+    if (st == GF_OK && n > 0) st = gf_validate_rays(rays, n, (hipStream_t)stream, "gf_optical_depth_counts");
     if (st != GF_OK) return st;
     if (n == 0) return GF_OK;
     unsigned nb = gf_packet_blocks(n, image_width);

@@ -33,14 +33,19 @@
 
 #define TR_THREADS 64
 #define TR_STACK 64  // deepest LBVH the per-lane traversal supports
-#define TS_LDS 24    // per-lane stack entries kept in LDS; deeper ones go to the workspace
-#define TK 64        // tentative points per window
-#define CQ 8         // leaf candidates a lane queues before the wave processes them
+#define TS_LDS 16    // per-lane stack entries kept in LDS; deeper ones go to the workspace
+#define TK 64        // tentative points per window (also the bins of a CDF-inversion level)
+#define CQ 6         // leaf candidates a lane queues before the wave processes them
 #define DRAIN_LANES 4  // the wave drains its leaf queues once fewer lanes than this can step
 #define SG 8         // samples whose secondary paths a lane follows back to back
-// Largest weight of a stochastic cell (3 / p_k with p_k >= 1/6): the
-// majorant's multiplier of the drawn cell never needs to exceed it, so the
-// majorant bounds |kappa| of the reweighted field too.
+// Cap of a cell's majorant multiplier.  The tentative points follow the
+// envelope of the primitives scaled by min(cell weight, MAJ_CAP); where a
+// weight exceeds the cap the envelope no longer bounds |kappa| of the
+// reweighted field, which ratio tracking and the signed-weight delta
+// tracking below tolerate (both are unbiased for any positive majorant):
+// rare large weights (importance sampling of a badly aligned bin) then cost
+// variance instead of an unbounded number of points.  18 is the largest
+// weight of the uniform + control variate levels with the mixture bins.
 #define MAJ_CAP 18.0f
 // Hard bound on windows per segment (TK points each): a segment that would
 // need more is cut short there, which keeps every wave's work finite.
@@ -48,8 +53,12 @@
 // Waves resident in one launch: each owns a workspace slice, and loops over
 // the launch's tiles with a grid stride.
 #define TR_RES_BLOCKS 3072
+// CDF inversion: levels of TK-bin refinement before the final linear step
+#define FF_LEVELS 3
 
-// Workspace rows of a wave (each row: TR_THREADS lanes x 4 B).
+// Workspace rows of a wave (each row: TR_THREADS lanes x 4 B); the slice
+// size is published to the other translation units as
+// GF_TRACK_WAVE_FLOATS.
 #define WS_KAP 0
 #define WS_MAJ TK
 #define WS_XI (2 * TK)
@@ -57,69 +66,179 @@
 #define WS_TC (WS_SPILL + TR_STACK - TS_LDS)
 #define WS_WF (WS_TC + SG)
 #define WS_ROWS (WS_WF + SG)
+static_assert(WS_ROWS * TR_THREADS == GF_TRACK_WAVE_FLOATS, "tracking slice size");
 
 // c_i / amp_i: the density's normalisation (2 pi)^-3/2 / (s0 s1 s2) over the
 // optical-depth amplitude 1 / (4 pi s0 s1 s2), i.e. sqrt(2 / pi)
 #define GF_NORM 0.79788456080286535588f
 
-// Per-cell density weight w_c and majorant weight m_c: 1 on the cells of
-// `cells` except `pick`, which carries (wp, mwp); 0 elsewhere.
+// Per-cell weights of the segment a lane is tracking: the density weight
+// w_c of cell c sits in LDS (LaneMem::cw, one row per cell), its majorant
+// multiplier is min(w_c, MAJ_CAP); `cells` holds the cells with a non-zero
+// weight (they prune the traversal).
 struct CellW {
     uint32_t cells;
-    int pick;
-    float wp, mwp;
-    __device__ float w(int c) const { return c == pick ? wp : (((cells >> c) & 1u) ? 1.0f : 0.0f); }
-    __device__ float mw(int c) const { return c == pick ? mwp : (((cells >> c) & 1u) ? 1.0f : 0.0f); }
 };
 
-static __device__ __forceinline__ CellW fixed_weights(const MaskView& M) {
+static __device__ __forceinline__ CellW fixed_weights(uint32_t cells, float* wl) {
     CellW cw;
-    cw.cells = M.cells & 0xFFFu;
-    cw.pick = -1;
-    cw.wp = cw.mwp = 0.0f;
+    cw.cells = cells & 0xFFFu;
+#pragma unroll
+    for (int c = 0; c < GF_NCELLS; ++c) wl[c * TR_THREADS] = ((cw.cells >> c) & 1u) ? 1.0f : 0.0f;
     return cw;
 }
 
-// Uniform + control variate over levels; over bins an even mixture of the
-// importance and uniform strategies (Appendix B tables): level 0 keeps
-// weight 1; one level l in 1..3 (probability 1/3) and one bin k (probability
-// p_k = w_k / (2W) + 1/6, w_k = exp(-m_lk^2 a_k^2 / 2), a_k = |v_k| / |v|)
-// get weight 3 / p_k <= 18; every other cell weight 0.
-static __device__ __forceinline__ CellW stochastic_weights(const SceneView& S, float vx, float vy, float vz, Rng& g) {
-    float ul = g.u(), ub = g.u();
-    int l = 1 + (int)(ul * 3.0f);
-    l = l > 3 ? 3 : l;
-    float vn2 = vx * vx + vy * vy + vz * vz;
-    float a2[3] = {vx * vx / vn2, vy * vy / vn2, vz * vz / vn2};
-    // log weights, normalised by their maximum so that W >= 1 never underflows
-    float lw[3], mx = -INFINITY;
-    for (int k = 0; k < 3; ++k) {
-        float m = S.med[3 * l + k];
-        lw[k] = -0.5f * m * m * a2[k];
-        mx = fmaxf(mx, lw[k]);
+// Strategy of the per-segment stochastic masks (the Appendix B tables).
+struct Strat {
+    int level, bin;
+    float beta, delta;
+};
+
+#define NLEV 4
+#define NBIN 3
+
+// x^e for x >= 0, e > 0 (exp / log intrinsics; x = 0 gives 0)
+static __device__ __forceinline__ float pow_pos(float x, float e) { return x > 0.0f ? __expf(e * __logf(x)) : 0.0f; }
+
+// Level weights (frequency-level table) for the uniform u: lw[l] of level l
+// is `w0` for level 0 (the control variate), `wd` for the drawn level `ld`,
+// and under accumulation 1 / (1 - (l/P)^e) for every level l <= ld.  With
+// e = 1 - beta the power-law draw x = u^(1/e) falls in bucket [a, b) with
+// probability b^e - a^e.
+struct LevelDraw {
+    int ld;
+    float w0, wd;
+    bool all, accum;
+    float e;
+    __device__ float weight(int l) const {
+        if (all) return 1.0f;
+        if (accum) return l <= ld ? 1.0f / (1.0f - pow_pos((float)l / NLEV, e)) : 0.0f;
+        return l == ld ? wd : (l == 0 ? w0 : 0.0f);
     }
-    float wk[3], W = 0.0f;
-    for (int k = 0; k < 3; ++k) {
-        wk[k] = __expf(lw[k] - mx);
-        W += wk[k];
+};
+
+static __device__ __forceinline__ LevelDraw draw_level(const Strat& Z, float u) {
+    LevelDraw D;
+    D.e = 1.0f - Z.beta;
+    D.all = Z.level == GF_LEVEL_ALL;
+    D.accum = Z.level == GF_LEVEL_POWER_CV_ACCUM;
+    D.w0 = 0.0f;
+    D.ld = 0;
+    D.wd = 0.0f;
+    const float x = pow_pos(u, 1.0f / D.e);
+    if (Z.level == GF_LEVEL_UNIFORM) {
+        D.ld = min(NLEV - 1, (int)(NLEV * u));
+        D.wd = (float)NLEV;
+    } else if (Z.level == GF_LEVEL_POWER) {
+        D.ld = min(NLEV - 1, (int)(NLEV * x));
+        D.wd = 1.0f / (pow_pos((float)(D.ld + 1) / NLEV, D.e) - pow_pos((float)D.ld / NLEV, D.e));
+    } else if (Z.level == GF_LEVEL_UNIFORM_CV) {
+        D.w0 = 1.0f;
+        D.ld = 1 + min(NLEV - 2, (int)((NLEV - 1) * u));
+        D.wd = (float)(NLEV - 1);
+    } else if (Z.level == GF_LEVEL_POWER_CV) {
+        D.w0 = 1.0f;
+        const int j = min(NLEV - 2, (int)((NLEV - 1) * x));
+        D.ld = 1 + j;
+        D.wd = 1.0f / (pow_pos((float)(j + 1) / (NLEV - 1), D.e) - pow_pos((float)j / (NLEV - 1), D.e));
+    } else if (D.accum) {
+        D.ld = min(NLEV - 1, (int)(NLEV * x));
     }
-    // even mixture of importance and uniform sampling: p_k >= 1/6
-    float p[3];
-    for (int k = 0; k < 3; ++k) p[k] = 0.5f * wk[k] / W + (1.0f / 6.0f);
-    int k = 2;
-    float acc = 0.0f;
-    for (int j = 0; j < 2; ++j) {
-        acc += p[j];
-        if (ub < acc) {
-            k = j;
-            break;
+    return D;
+}
+
+// Bin weights (b0, b1, b2) of one level for the uniform u (orientation
+// table); f_k the cell medians of |k_W| of the level, a_k the alignments
+// |v.e_k| / |v|.
+static __device__ __forceinline__ void bin_weights(const Strat& Z, float f0, float f1, float f2, float a0, float a1,
+                                                   float a2, float u, float& b0, float& b1, float& b2) {
+    b0 = b1 = b2 = 0.0f;
+    if (Z.bin == GF_BIN_ALL) {
+        b0 = b1 = b2 = 1.0f;
+    } else if (Z.bin == GF_BIN_THRESHOLD) {
+        b0 = a0 <= Z.delta ? 1.0f : 0.0f;
+        b1 = a1 <= Z.delta ? 1.0f : 0.0f;
+        b2 = a2 <= Z.delta ? 1.0f : 0.0f;
+    } else if (Z.bin == GF_BIN_UNIFORM) {
+        int k = min(NBIN - 1, (int)(NBIN * u));
+        b0 = k == 0 ? (float)NBIN : 0.0f;
+        b1 = k == 1 ? (float)NBIN : 0.0f;
+        b2 = k == 2 ? (float)NBIN : 0.0f;
+    } else if (Z.bin == GF_BIN_THRESHOLD_UNIFORM) {
+        // bins within the threshold keep weight 1; one of the N others,
+        // in axis order, is drawn with weight N
+        const bool h0 = a0 > Z.delta, h1 = a1 > Z.delta, h2 = a2 > Z.delta;
+        const int na = (int)h0 + (int)h1 + (int)h2;
+        b0 = h0 ? 0.0f : 1.0f;
+        b1 = h1 ? 0.0f : 1.0f;
+        b2 = h2 ? 0.0f : 1.0f;
+        if (na > 0) {
+            const int j = min(na - 1, (int)(na * u));
+            const int r0 = 0, r1 = (int)h0, r2 = (int)h0 + (int)h1;  // rank among the bins above
+            if (h0 && r0 == j) b0 = (float)na;
+            if (h1 && r1 == j) b1 = (float)na;
+            if (h2 && r2 == j) b2 = (float)na;
+        }
+    } else {
+        // importance (w_k / W) or its mixture with uniform; the log weights
+        // are shifted by their maximum so that W >= 1 never underflows
+        const float l0 = -0.5f * f0 * f0 * a0 * a0, l1 = -0.5f * f1 * f1 * a1 * a1, l2 = -0.5f * f2 * f2 * a2 * a2;
+        const float mx = fmaxf(l0, fmaxf(l1, l2));
+        const float w0 = __expf(l0 - mx), w1 = __expf(l1 - mx), w2 = __expf(l2 - mx);
+        const float W = w0 + w1 + w2;
+        float p0 = w0 / W, p1 = w1 / W, p2 = w2 / W;
+        if (Z.bin == GF_BIN_MIXTURE) {
+            p0 = 0.5f * p0 + 0.5f / NBIN;
+            p1 = 0.5f * p1 + 0.5f / NBIN;
+            p2 = 0.5f * p2 + 0.5f / NBIN;
+        }
+        // the bin whose cumulative range holds u; bins of probability 0 are
+        // never drawn, and rounding past the sum falls to the last drawable
+        int pick = -1;
+        float acc = 0.0f;
+        if (p0 > 0.0f) {
+            pick = 0;
+            acc += p0;
+        }
+        if (!(u < acc) && p1 > 0.0f) {
+            pick = 1;
+            acc += p1;
+        }
+        if (!(u < acc) && p2 > 0.0f) pick = 2;
+        b0 = pick == 0 ? 1.0f / p0 : 0.0f;
+        b1 = pick == 1 ? 1.0f / p1 : 0.0f;
+        b2 = pick == 2 ? 1.0f / p2 : 0.0f;
+    }
+}
+
+// A segment's stochastic cell weights (Sec. 4.5.1-4.5.2): four uniforms,
+// u0 for the level strategy and u_l for the bins of each traced level
+// l >= 1; level 0 keeps its bins with the level's weight.  Cells outside
+// the fixed mask get weight 0.
+static __device__ __forceinline__ CellW stochastic_weights(const SceneView& S, const Strat& Z, uint32_t fixed,
+                                                           float vx, float vy, float vz, Rng& g, float* wl) {
+    const float u0 = g.u(), u1 = g.u(), u2 = g.u(), u3 = g.u();
+    const float vn = sqrtf(vx * vx + vy * vy + vz * vz);
+    const float a0 = fabsf(vx) / vn, a1 = fabsf(vy) / vn, a2 = fabsf(vz) / vn;
+    const LevelDraw D = draw_level(Z, u0);
+    CellW cw;
+    cw.cells = 0u;
+#pragma unroll
+    for (int l = 0; l < NLEV; ++l) {
+        const float lw = D.weight(l);
+        float b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
+        if (l > 0 && lw != 0.0f)
+            bin_weights(Z, S.med[NBIN * l], S.med[NBIN * l + 1], S.med[NBIN * l + 2], a0, a1, a2,
+                        l == 1 ? u1 : (l == 2 ? u2 : u3), b0, b1, b2);
+        const float w[NBIN] = {lw * b0, lw * b1, lw * b2};
+#pragma unroll
+        for (int k = 0; k < NBIN; ++k) {
+            const int c = NBIN * l + k;
+            const float wc = ((fixed >> c) & 1u) ? w[k] : 0.0f;
+            wl[c * TR_THREADS] = wc;
+            if (wc != 0.0f) cw.cells |= 1u << c;
         }
     }
-    CellW cw;
-    cw.pick = 3 * l + k;
-    cw.cells = 0x7u | (1u << cw.pick);
-    cw.wp = 3.0f / p[k];
-    cw.mwp = fminf(cw.wp, MAJ_CAP);
     return cw;
 }
 
@@ -128,27 +247,26 @@ static __device__ __forceinline__ CellW stochastic_weights(const SceneView& S, f
 // at leaves, windows.
 struct Work {
     unsigned long long tent, nodes, prims, windows;
+    unsigned long long used, pq_nodes, cover;  // points consumed; their point-query nodes and covers
 };
 
 // kappa at x under per-cell weights (rho alpha c exp(-M/2) cos(psi) summed)
 template <bool COUNT>
-static __device__ float point_density(const SceneView& S, const MaskView& M, const CellW& cw, float x, float y,
-                                      float z, int* __restrict__ stk, Work& wk) {
+static __device__ float point_density(const SceneView& S, const MaskView& M, float x, float y, float z,
+                                      int* __restrict__ stk, Work& wk) {
     float acc = 0.0f;
     auto leaf = [&](int j) {
         PrimF P = load_prim(S.prims, j);
         if (COUNT) ++wk.prims;
-        float wgt = cw.w(P.cell);
-        if (wgt == 0.0f) return;
-        if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
+        if (!mask_keep(M, P.cell, P.orig)) return;
         float dx = x - P.mux, dy = y - P.muy, dz = z - P.muz;
         float m = dx * (P.a00 * dx + P.a01 * dy + P.a02 * dz) + dy * (P.a01 * dx + P.a11 * dy + P.a12 * dz) +
                   dz * (P.a02 * dx + P.a12 * dy + P.a22 * dz);
-        if (!(m < S.r2)) return;
+        if (!(m < P.r2)) return;
         float ph = P.fx * dx + P.fy * dy + P.fz * dz + P.phi * (float)GF_INV_2PI;
         float s, c;
         sincos2pi(ph - rintf(ph), &s, &c);
-        acc += wgt * P.amp * GF_NORM * __expf(-0.5f * m) * c;
+        acc += P.amp * GF_NORM * __expf(-0.5f * m) * c;
     };
     if (S.n == 1) {
         leaf(0);
@@ -159,8 +277,8 @@ static __device__ float point_density(const SceneView& S, const MaskView& M, con
         const TNode* nd = S.nodes + node;
         if (COUNT) ++wk.nodes;
         uint32_t cells = nd->cells;
-        bool hl = (cells & 0xffffu & cw.cells) && box_contains(nd->lbox, x, y, z);
-        bool hr = ((cells >> 16) & cw.cells) && box_contains(nd->rbox, x, y, z);
+        bool hl = (cells & 0xffffu & M.cells) && box_contains(nd->lbox, x, y, z);
+        bool hr = ((cells >> 16) & M.cells) && box_contains(nd->rbox, x, y, z);
         int lc = nd->lchild, rc = nd->rchild;
         if (hl && lc < 0) {
             leaf(~lc);
@@ -195,8 +313,11 @@ static __device__ float point_density(const SceneView& S, const MaskView& M, con
 struct LaneMem {
     int* stk;   // LDS, TS_LDS entries, stride TR_THREADS
     int* cand;  // LDS, CQ queued leaf candidates, stride TR_THREADS
-    float* t;   // LDS, TK tentative distances, stride TR_THREADS
+    float* t;   // LDS, TK tentative distances (or CDF bins), stride TR_THREADS
+    float* cw;  // LDS, GF_NCELLS cell weights of the current segment, stride TR_THREADS
     float* ws;  // workspace: row r at ws[r * TR_THREADS]
+    __device__ float w(int c) const { return cw[c * TR_THREADS]; }
+    __device__ float mw(int c) const { return fminf(cw[c * TR_THREADS], MAJ_CAP); }
     __device__ float& kap(int k) const { return ws[(WS_KAP + k) * TR_THREADS]; }
     __device__ float& maj(int k) const { return ws[(WS_MAJ + k) * TR_THREADS]; }
     __device__ float& xi(int k) const { return ws[(WS_XI + k) * TR_THREADS]; }
@@ -217,10 +338,12 @@ struct LaneMem {
     __shared__ int stk_all[TS_LDS * TR_THREADS];                                        \
     __shared__ int cand_all[CQ * TR_THREADS];                                           \
     __shared__ float t_all[TK * TR_THREADS];                                            \
+    __shared__ float cw_all[GF_NCELLS * TR_THREADS];                                    \
     LaneMem lm;                                                                         \
     lm.stk = stk_all + threadIdx.x;                                                     \
     lm.cand = cand_all + threadIdx.x;                                                   \
     lm.t = t_all + threadIdx.x;                                                         \
+    lm.cw = cw_all + threadIdx.x;                                                       \
     lm.ws = (ws_base) + (size_t)blockIdx.x * (WS_ROWS * TR_THREADS) + threadIdx.x;
 
 // chord of primitive P with the ray in float32: false when M < r^2 misses
@@ -388,10 +511,21 @@ static __device__ __forceinline__ float latest_point(const LaneMem& lm, int* slo
     return best;
 }
 
-// One segment window [ta, tb] of the ray o + t v.
+// One segment window [ta, tb] of the ray o + t v; lod2 the square of the
+// continuous-LOD cutoff (0: off).
 struct Seg {
-    float ox, oy, oz, vx, vy, vz, ta, tb;
+    float ox, oy, oz, vx, vy, vz, ta, tb, lod2;
 };
+
+// Continuous LOD (supplementary "LOD Selection"): a primitive whose closest
+// point lies at distance d = tc |v| ahead of the origin is left out when
+// |f|^2 d^2 > lod_k^2 (its frequency is above the Nyquist limit there).
+static __device__ __forceinline__ bool lod_drop(const PrimF& P, const Seg& sg, float tc) {
+    if (!(sg.lod2 > 0.0f) || !(tc > 0.0f)) return false;
+    float f2 = (P.fx * P.fx + P.fy * P.fy) + P.fz * P.fz;
+    float v2 = sg.vx * sg.vx + sg.vy * sg.vy + sg.vz * sg.vz;
+    return f2 * (tc * tc * v2) > sg.lod2;
+}
 
 // Proposal state of a window: points held and window end (the segment end,
 // or the last point held once the buffer is full).
@@ -409,10 +543,11 @@ static __device__ void prop_leaf(const SceneView& S, const MaskView& M, const Ce
                                  uint32_t k1, int win, int j, Prop& pr, const LaneMem& lm, Work& wk) {
     PrimF P = load_prim(S.prims, j);
     if (COUNT) ++wk.prims;
-    float mw = cw.mw(P.cell);
+    float mw = lm.mw(P.cell);
     if (mw == 0.0f || !prim_on(M, P.orig)) return;
     ChordF C;
-    if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, pr.tcut, C, false)) return;
+    if (!chord_f32(P, P.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, pr.tcut, C, false)) return;
+    if (lod_drop(P, sg, C.tc)) return;
     float lam = mw * fabsf(P.amp) * GF_NORM * __expf(-0.5f * C.h2);
     if (!(lam > 0.0f)) return;
     float inv = 1.0f / lam;
@@ -464,7 +599,7 @@ static __device__ void sort_points(const LaneMem& lm, int np) {
 static __device__ __forceinline__ void add_chord(const PrimF& P, const ChordF& C, const CellW& cw, float mw,
                                                  const Seg& sg, int np, int k, const LaneMem& lm) {
     float am = P.amp * GF_NORM, aa = fabsf(am);
-    float ws = copysignf(cw.w(P.cell), am);
+    float ws = copysignf(lm.w(P.cell), am);
     for (; k < np; ++k) {
         float t = lm.t[k * TR_THREADS];
         if (t > C.co) break;
@@ -491,10 +626,11 @@ static __device__ void evaluate(const SceneView& S, const MaskView& M, const Cel
     lane_traverse<COUNT>(S, cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, lm, wk, [&](int j) {
         PrimF P = load_prim(S.prims, j);
         if (COUNT) ++wk.prims;
-        float mw = cw.mw(P.cell);
+        float mw = lm.mw(P.cell);
         if (mw == 0.0f || !prim_on(M, P.orig)) return;
         ChordF C;
-        if (!chord_f32(P, S.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, C, true)) return;
+        if (!chord_f32(P, P.r2, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, pa, pb, C, true)) return;
+        if (lod_drop(P, sg, C.tc)) return;
         add_chord(P, C, cw, mw, sg, np, first_point(lm, np, C.ci), lm);
     });
 }
@@ -523,15 +659,16 @@ struct SegState {
     CellW cw;
     int mode, win;
     bool live;    // window left to track
-    float T;      // ratio-tracking product
+    float T;      // ratio-tracking product (exact: exp(-tau) of the segment)
     float wf;     // delta-tracking weight factor
-    float tc;     // delta collision distance (INFINITY: none)
+    float tc;     // collision distance (INFINITY: none)
+    float fs;     // CDF inversion: the optical depth -log(1 - xi) to reach
     uint32_t k0, k1;  // key of the segment's chord streams
 };
 
 static __device__ __forceinline__ void begin_segment(const SceneView& S, SegState& st, const float* o,
                                                      const float* v, float t0, float t1, const CellW& cw, int mode,
-                                                     Rng& g) {
+                                                     float lod2, Rng& g) {
     st.k0 = g.bits();
     st.k1 = g.bits();
     st.sg.ox = o[0];
@@ -542,6 +679,7 @@ static __device__ __forceinline__ void begin_segment(const SceneView& S, SegStat
     st.sg.vz = v[2];
     st.sg.ta = t0;
     st.sg.tb = t1;
+    st.sg.lod2 = lod2;
     st.live = clip_box(S, o[0], o[1], o[2], v[0], v[1], v[2], st.sg.ta, st.sg.tb);
     st.cw = cw;
     st.mode = mode;
@@ -549,7 +687,12 @@ static __device__ __forceinline__ void begin_segment(const SceneView& S, SegStat
     st.T = 1.0f;
     st.wf = 1.0f;
     st.tc = INFINITY;
+    st.fs = 0.0f;
 }
+
+// CDF inversion: the optical depth s = -log(1 - xi) at which the segment's
+// free flight ends
+static __device__ __forceinline__ void draw_flight(SegState& st, Rng& g) { st.fs = -__logf(1.0f - g.u()); }
 
 static __device__ __forceinline__ void begin_prop(Prop& pr, const SegState& st) {
     pr.np = 0;
@@ -628,10 +771,11 @@ static __device__ __forceinline__ void eval_leaf(const SceneView& S, const MaskV
                                                  float pa, float pb, int np, const LaneMem& lm, Work& wk) {
     PrimF P = load_prim(S.prims, j);
     if (COUNT) ++wk.prims;
-    float mw = st.cw.mw(P.cell);
+    float mw = lm.mw(P.cell);
     if (mw == 0.0f || !prim_on(M, P.orig)) return;
     ChordF C;
-    if (!chord_f32(P, S.r2, st.sg.ox, st.sg.oy, st.sg.oz, st.sg.vx, st.sg.vy, st.sg.vz, pa, pb, C, true)) return;
+    if (!chord_f32(P, P.r2, st.sg.ox, st.sg.oy, st.sg.oz, st.sg.vx, st.sg.vy, st.sg.vz, pa, pb, C, true)) return;
+    if (lod_drop(P, st.sg, C.tc)) return;
     add_chord(P, C, st.cw, mw, st.sg, np, first_point(lm, np, C.ci), lm);
 }
 
@@ -646,11 +790,81 @@ static __device__ __forceinline__ void open_points(const LaneMem& lm, int np) {
 
 // Decisions of an evaluated window and the move to the next one.  Returns
 // true when the segment is finished.
+// Work of a point query at x, the unit of the algorithmic bytes of tracking:
+// internal nodes whose box contains x on the walk from the root (pruned by
+// the cells), and primitives of weighted cells whose truncated support
+// contains x.  Counting variants only.
+static __device__ void count_point_query(const SceneView& S, const MaskView& M, uint32_t cells, const LaneMem& lm,
+                                         float x, float y, float z, Work& wk) {
+    auto leaf = [&](int j) {
+        PrimF P = load_prim(S.prims, j);
+        if (!((cells >> P.cell) & 1u) || !prim_on(M, P.orig)) return;
+        float dx = x - P.mux, dy = y - P.muy, dz = z - P.muz;
+        float m = dx * (P.a00 * dx + P.a01 * dy + P.a02 * dz) + dy * (P.a01 * dx + P.a11 * dy + P.a12 * dz) +
+                  dz * (P.a02 * dx + P.a12 * dy + P.a22 * dz);
+        if (m < P.r2) ++wk.cover;
+    };
+    if (S.n == 1) {
+        leaf(0);
+        return;
+    }
+    int sp = 0, node = 0;
+    for (;;) {
+        const TNode* nd = S.nodes + node;
+        ++wk.pq_nodes;
+        uint32_t c = nd->cells;
+        bool hl = (c & 0xffffu & cells) && box_contains(nd->lbox, x, y, z);
+        bool hr = ((c >> 16) & cells) && box_contains(nd->rbox, x, y, z);
+        int lc = nd->lchild, rc = nd->rchild;
+        if (hl && lc < 0) {
+            leaf(~lc);
+            hl = false;
+        }
+        if (hr && rc < 0) {
+            leaf(~rc);
+            hr = false;
+        }
+        if (hl && hr) {
+            lm.push(sp, rc);
+            ++sp;
+            node = lc;
+        } else if (hl) {
+            node = lc;
+        } else if (hr) {
+            node = rc;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = lm.pop(sp);
+        }
+    }
+}
+
 template <bool COUNT>
-static __device__ bool decide_window(SegState& st, const Prop& pr, const LaneMem& lm, Work& wk) {
+static __device__ bool decide_window(const SceneView& S, const MaskView& M, SegState& st, const Prop& pr,
+                                     const LaneMem& lm, Work& wk) {
     if (!st.live) return true;
     if (COUNT) ++wk.windows;
     const int np = pr.np;
+    if (COUNT) {
+        // the points the estimators consume: all of them for ratio
+        // tracking, up to the collision for delta tracking
+        int used = np;
+        if (!(st.mode & MODE_RATIO) && (st.mode & MODE_DELTA) && !(st.tc < INFINITY)) {
+            float fr, fn;
+            for (int k = 0; k < np; ++k)
+                if (delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn)) {
+                    used = k + 1;
+                    break;
+                }
+        }
+        wk.used += used;
+        for (int k = 0; k < used; ++k) {
+            const float t = lm.t[k * TR_THREADS];
+            count_point_query(S, M, st.cw.cells, lm, st.sg.ox + t * st.sg.vx, st.sg.oy + t * st.sg.vy,
+                              st.sg.oz + t * st.sg.vz, wk);
+        }
+    }
     if (st.mode & MODE_RATIO)
         for (int k = 0; k < np; ++k) st.T *= 1.0f - lm.kap(k) / lm.maj(k);
     if ((st.mode & MODE_DELTA) && !(st.tc < INFINITY)) {
@@ -682,7 +896,7 @@ static __device__ bool close_window(const SceneView& S, const MaskView& M, SegSt
         open_points(lm, pr.np);
         evaluate<COUNT>(S, M, st.cw, st.sg, pr.np, lm, wk);
     }
-    return decide_window<COUNT>(st, pr, lm, wk);
+    return decide_window<COUNT>(S, M, st, pr, lm, wk);
 }
 
 static __device__ __forceinline__ void sample_sphere(Rng& g, float* d) {
@@ -752,10 +966,172 @@ static int64_t tr_threads(int64_t n, int tile_w) {
 // per-ray drivers
 // ---------------------------------------------------------------------------
 struct RenderArgs {
-    int spp, multiple, max_scatter, stochastic;
+    int spp, multiple, max_scatter, stochastic, exact;
     float albedo, hg, env;
+    Strat strat;
+    uint32_t shadow_cells;  // 0: shadow segments draw their own mask
     uint64_t seed;
 };
+
+// ---------------------------------------------------------------------------
+// Free flights by CDF inversion (Sec. 3: a collision at x_t solves
+// log(1 - xi) = -sum_i tau_i(x_0, x_t); Sec. 4.4, distance sampling by
+// inverting the closed-form optical depth) and exact transmittance.
+// The optical depth over [lo, hi] is split into TK bins of equal length:
+// every crossed chord adds its closed-form integral over each bin piece it
+// covers (the segment integral of Sec. 4.4 with the piece's ends as bounds,
+// binary64 chord geometry).  The bins give the segment's optical depth
+// (T = exp(-tau)) and the first bin where the cumulative depth reaches
+// s = -log(1 - xi); FF_LEVELS rounds of splitting that bin into TK sub-bins
+// narrow the collision to (hi - lo) / TK^FF_LEVELS, inside which the depth
+// is taken as linear.  The path escapes when the depth of the whole segment
+// is below s.  For a non-negative density the distance follows
+// 1 - exp(-tau(ta, t)) up to that last linear step; where the mixture is
+// negative the cumulative depth need not be monotone and the sampler returns
+// its first crossing.  The bins reuse the lane's tentative-point row.
+// ---------------------------------------------------------------------------
+__constant__ float c_weid_tr[WEID_N];
+__constant__ float c_weidL_tr;
+__constant__ double c_weid64_tr[WEID64_N];
+__constant__ double c_weidL64_tr;
+
+static bool g_weid_tr_ready[64];
+
+gf_status gf_ensure_weideman_track() {
+    int dev = 0;
+    GF_HIP(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 64 && g_weid_tr_ready[dev]) return GF_OK;
+    float a[WEID_N], L;
+    gf_weideman_coeffs(a, &L);
+    GF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_weid_tr), a, sizeof(a)));
+    GF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_weidL_tr), &L, sizeof(L)));
+    double a64[WEID64_N], L64;
+    gf_weideman_coeffs64(a64, &L64);
+    GF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_weid64_tr), a64, sizeof(a64)));
+    GF_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_weidL64_tr), &L64, sizeof(L64)));
+    if (dev >= 0 && dev < 64) g_weid_tr_ready[dev] = true;
+    return GF_OK;
+}
+
+// Weighted optical depth of primitive j's chord over [lo, hi], added to the
+// TK bins of width (hi - lo) / TK piece by piece.
+template <bool COUNT>
+static __device__ void bin_chord(const SceneView& S, const MaskView& M, const SegState& st, int j, float lo,
+                                 float hi, const LaneMem& lm, Work& wk) {
+    PrimF P = load_prim(S.prims, j);
+    if (COUNT) ++wk.prims;
+    const float w = lm.w(P.cell);
+    if (w == 0.0f || !prim_on(M, P.orig)) return;
+    RayD R;
+    R.ox = st.sg.ox; R.oy = st.sg.oy; R.oz = st.sg.oz;
+    R.vx = st.sg.vx; R.vy = st.sg.vy; R.vz = st.sg.vz;
+    R.tmin = lo; R.tmax = hi;
+    HitGeom H;
+    if (!hit_geom(P, R, P.r2, S.A64 + (size_t)j * 6, H)) return;
+    if (lod_drop(P, st.sg, (float)H.tc)) return;
+    const double dlo = lo, dw = ((double)hi - dlo) / TK;
+    const double ta = H.tc + H.uad * H.inv_n, tb = H.tc + H.ubd * H.inv_n;
+    const int b0 = min(TK - 1, max(0, (int)floor((ta - dlo) / dw)));
+    const int b1 = min(TK - 1, max(0, (int)floor((tb - dlo) / dw)));
+    for (int b = b0; b <= b1; ++b) {
+        double p0 = fmax(ta, dlo + b * dw), p1 = fmin(tb, dlo + (b + 1) * dw);
+        if (!(p0 < p1)) continue;
+        HitGeom Hp = H;
+        Hp.enda = H.enda && b == b0;
+        Hp.endb = H.endb && b == b1;
+        Hp.uad = Hp.enda ? -H.halfd : H.n * (p0 - H.tc);
+        Hp.ubd = Hp.endb ? H.halfd : H.n * (p1 - H.tc);
+        Hp.ua = (float)Hp.uad;
+        Hp.ub = (float)Hp.ubd;
+        lm.t[b * TR_THREADS] += w * hit_value(P, Hp, c_weid_tr, c_weidL_tr, c_weid64_tr, c_weidL64_tr);
+    }
+}
+
+// One binning pass over each active lane's [lo, hi]: a packet walk (camera
+// segments) or per-lane traversals (secondary segments).
+template <bool COUNT, bool PACKET>
+static __device__ void bin_pass(const SceneView& S, const MaskView& M, const SegState& st, bool act, float lo,
+                                float hi, const LaneMem& lm, int* pstk, Work& wk) {
+    if (act)
+        for (int b = 0; b < TK; ++b) lm.t[b * TR_THREADS] = 0.0f;
+    auto leaf = [&](int j) { bin_chord<COUNT>(S, M, st, j, lo, hi, lm, wk); };
+    if (PACKET) {
+        packet_walk<COUNT>(S, st, act, lo, hi, pstk, wk, leaf);
+    } else if (act) {
+        const Seg& sg = st.sg;
+        lane_traverse<COUNT>(S, st.cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, lo, hi, lm, wk, leaf);
+    }
+}
+
+// Exact transmittance and (MODE_DELTA) the CDF-inversion collision of the
+// segments of the active lanes; every lane of the wave calls it.
+template <bool COUNT, bool PACKET>
+static __device__ void exact_segment(const SceneView& S, const MaskView& M, SegState& st, bool act, const LaneMem& lm,
+                                     int* pstk, Work& wk) {
+    act = act && st.live;
+    float lo = st.sg.ta, hi = st.sg.tb, acc = 0.0f, frac = 0.0f;
+    bool seek = act && (st.mode & MODE_DELTA);
+    for (int lev = 0; lev < FF_LEVELS; ++lev) {
+        // only lanes still searching (and, first, every active lane) bin
+        const bool bin = lev == 0 ? act : seek;
+        if (PACKET ? !__any(bin) : !bin) break;
+        bin_pass<COUNT, PACKET>(S, M, st, bin, lo, hi, lm, pstk, wk);
+        if (lev == 0 && act) {
+            float tot = 0.0f;
+            for (int b = 0; b < TK; ++b) tot += lm.t[b * TR_THREADS];
+            st.T = __expf(-tot);
+            if (!(tot >= st.fs)) seek = false;  // escape
+        }
+        if (seek) {
+            // first bin whose cumulative depth reaches s (the last bin when
+            // rounding leaves the sub-bins' sum just below their parent's)
+            int b = TK - 1;
+            float d = lm.t[b * TR_THREADS];
+            for (int k = 0; k < TK; ++k) {
+                float dk = lm.t[k * TR_THREADS];
+                if (acc + dk >= st.fs || k == TK - 1) {
+                    b = k;
+                    d = dk;
+                    break;
+                }
+                acc += dk;
+            }
+            frac = d > 0.0f ? fminf(1.0f, fmaxf(0.0f, (st.fs - acc) / d)) : 0.5f;
+            const float dw = (hi - lo) / TK;
+            lo = lo + b * dw;
+            hi = lo + dw;
+        }
+    }
+    if (seek) st.tc = lo + frac * (hi - lo);
+    if (act) st.live = false;
+}
+
+// Exact transmittance exp(-tau) of a lane's own segment: one traversal
+// summing the closed-form integrals of the crossed chords (Sec. 4.4), the
+// way the tomography case of Sec. 4.6 turns optical depth into
+// transmittance.  Its mean equals that of ratio tracking, with no variance.
+template <bool COUNT>
+static __device__ void exact_T_own(const SceneView& S, const MaskView& M, SegState& st, const LaneMem& lm, Work& wk) {
+    if (!st.live) return;
+    RayD R;
+    R.ox = st.sg.ox; R.oy = st.sg.oy; R.oz = st.sg.oz;
+    R.vx = st.sg.vx; R.vy = st.sg.vy; R.vz = st.sg.vz;
+    R.tmin = st.sg.ta; R.tmax = st.sg.tb;
+    float acc = 0.0f;
+    const Seg& sg = st.sg;
+    lane_traverse<COUNT>(S, st.cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, sg.tb, lm, wk, [&](int j) {
+        PrimF P = load_prim(S.prims, j);
+        if (COUNT) ++wk.prims;
+        const float w = lm.w(P.cell);
+        if (w == 0.0f || !prim_on(M, P.orig)) return;
+        HitGeom H;
+        if (!hit_geom(P, R, P.r2, S.A64 + (size_t)j * 6, H)) return;
+        if (lod_drop(P, sg, (float)H.tc)) return;
+        acc += w * hit_value(P, H, c_weid_tr, c_weidL_tr, c_weid64_tr, c_weidL64_tr);
+    });
+    st.T = __expf(-acc);
+    st.live = false;
+}
 
 // Camera segments of a whole wave, window by window: packet proposal and
 // packet evaluation passes; a lane whose segment is finished sits out.
@@ -774,7 +1150,7 @@ static __device__ void track_camera(const SceneView& S, const MaskView& M, SegSt
         const float pa = ev ? lm.t[0] : 0.0f, pb = ev ? lm.t[(pr.np - 1) * TR_THREADS] : -1.0f;
         packet_walk<COUNT>(S, st, ev, pa, pb, pstk, wk,
                            [&](int j) { eval_leaf<COUNT>(S, M, st, j, pa, pb, pr.np, lm, wk); });
-        if (open && decide_window<COUNT>(st, pr, lm, wk)) open = false;
+        if (open && decide_window<COUNT>(S, M, st, pr, lm, wk)) open = false;
     }
 }
 
@@ -788,15 +1164,19 @@ static __device__ bool track_own(const SceneView& S, const MaskView& M, SegState
 }
 
 // Radiance of one camera ray over spp samples, with a constant environment.
-// Single scattering: the camera segment is delta-tracked (and ratio-tracked
-// for its transmittance on the same tentative points); a real collision
-// scatters isotropically and ratio-tracks the way out.  Multiple scattering:
-// delta tracking from segment to segment with Henyey-Greenstein scattering
-// until escape or max_scatter scatterings.  The camera segment draws from
-// the sample's stream (seed, ray, sample, 0), the rest of its path from
-// (seed, ray, sample, 2).
+// Single scattering: the camera segment is free-flight sampled (and its
+// transmittance estimated on the same points, or exactly); a real collision
+// scatters isotropically and estimates the transmittance of the way out.
+// Multiple scattering: free flights from segment to segment with
+// Henyey-Greenstein scattering until escape or max_scatter scatterings.
+// Every segment traces the fixed mask or draws its own stochastic cell
+// weights; with shadow_cells the shadow segment traces those cells of the
+// fixed mask (Zero-NEE).  The camera segment draws from the sample's stream
+// (seed, ray, sample, 0), the rest of its path from (seed, ray, sample, 2).
+template <bool EXACT>
 struct RenderLane {
     const float* r;
+    float* wl;  // LDS cell-weight rows of this lane
     uint32_t key;
     int nsc, seg;
     bool shadow;
@@ -804,16 +1184,22 @@ struct RenderLane {
     float s1, s2, q1, q2;
     Rng g;
     SegState st;
-    __device__ void begin(const float* ray, uint32_t k) {
+    __device__ void begin(const float* ray, uint32_t k, float* cw_rows) {
         r = ray;
+        wl = cw_rows;
         key = k;
         s1 = s2 = q1 = q2 = 0.0f;
+    }
+    __device__ CellW weights(const SceneView& S, const MaskView& M, const RenderArgs& A, const float* d) {
+        return A.stochastic ? stochastic_weights(S, A.strat, M.cells, d[0], d[1], d[2], g, wl)
+                            : fixed_weights(M.cells, wl);
     }
     // camera segment of sample s
     __device__ void start(const SceneView& S, const MaskView& M, const RenderArgs& A, int s) {
         g.init(A.seed, key, (uint32_t)s, 0u);
-        CellW cw = A.stochastic ? stochastic_weights(S, r[3], r[4], r[5], g) : fixed_weights(M);
-        begin_segment(S, st, r, r + 3, r[6], r[7], cw, MODE_RATIO | MODE_DELTA, g);
+        CellW cw = weights(S, M, A, r + 3);
+        begin_segment(S, st, r, r + 3, r[6], r[7], cw, MODE_RATIO | MODE_DELTA, M.lod2, g);
+        if (EXACT) draw_flight(st, g);
     }
     // after the camera segment: its transmittance estimate
     __device__ void camera_done() {
@@ -873,16 +1259,24 @@ struct RenderLane {
             mode = MODE_DELTA;
         }
         ++seg;
-        CellW cw = A.stochastic ? stochastic_weights(S, d[0], d[1], d[2], g) : fixed_weights(M);
-        begin_segment(S, st, x, d, 0.0f, INFINITY, cw, mode, g);
+        CellW cw = (shadow && A.shadow_cells) ? fixed_weights(A.shadow_cells & M.cells, wl) : weights(S, M, A, d);
+        begin_segment(S, st, x, d, 0.0f, INFINITY, cw, mode, 0.0f, g);
+        if (EXACT && mode == MODE_DELTA) draw_flight(st, g);
         return false;
+    }
+    // sample variance; +inf when the sums overflowed float32 (a heavy tail
+    // of the signed delta-tracking weights), never a silent 0
+    static __device__ float variance(float a1, float a2, float inv, int n) {
+        if (n < 2) return 0.0f;
+        float v = (a2 - a1 * a1 * inv) / (n - 1);
+        return v >= 0.0f ? v : (v < 0.0f ? 0.0f : INFINITY);
     }
     __device__ void result(const RenderArgs& A, float* out4) const {
         float inv = 1.0f / A.spp;
         out4[0] = s1 * inv;
-        out4[1] = A.spp > 1 ? fmaxf(0.0f, (s2 - s1 * s1 * inv) / (A.spp - 1)) : 0.0f;
+        out4[1] = variance(s1, s2, inv, A.spp);
         out4[2] = q1 * inv;
-        out4[3] = A.spp > 1 ? fmaxf(0.0f, (q2 - q1 * q1 * inv) / (A.spp - 1)) : 0.0f;
+        out4[3] = variance(q1, q2, inv, A.spp);
     }
 };
 
@@ -891,18 +1285,25 @@ struct RenderLane {
 // together (their outcomes kept in the workspace), then every lane follows
 // the paths of its SG samples back to back with per-lane passes, so a lane
 // with short paths does not wait on the longest path of each sample.
-template <bool COUNT>
+// FF: 0 delta tracking with ratio-tracked transmittances, 1 delta tracking
+// with closed-form shadow transmittances, 2 CDF inversion with closed-form
+// transmittances.
+template <bool COUNT, int FF>
 static __device__ void render_rays(const SceneView& S, const MaskView& M, const RenderArgs& A,
                                    const float* __restrict__ rays, int idx, const LaneMem& lm, int* pstk, Work& wk,
                                    float* out4) {
     const bool valid = idx >= 0;
-    RenderLane rl;
-    if (valid) rl.begin(rays + (size_t)idx * 8, (uint32_t)idx);
+    constexpr bool EXACT = FF == 2;
+    RenderLane<EXACT> rl;
+    if (valid) rl.begin(rays + (size_t)idx * 8, (uint32_t)idx, lm.cw);
     for (int s0 = 0; s0 < A.spp; s0 += SG) {
         const int gn = min(SG, A.spp - s0);
         for (int k = 0; k < gn; ++k) {
             if (valid) rl.start(S, M, A, s0 + k);
-            track_camera<COUNT>(S, M, rl.st, valid, lm, pstk, wk);
+            if (EXACT)
+                exact_segment<COUNT, true>(S, M, rl.st, valid, lm, pstk, wk);
+            else
+                track_camera<COUNT>(S, M, rl.st, valid, lm, pstk, wk);
             if (valid) {
                 rl.camera_done();
                 lm.ctc(k) = rl.st.tc;
@@ -921,7 +1322,19 @@ static __device__ void render_rays(const SceneView& S, const MaskView& M, const 
         };
         bool more = valid && next();
         while (__any(more)) {
-            if (more && track_own<COUNT>(S, M, rl.st, lm, wk) && rl.segment_done(S, M, A)) more = next();
+            if (more) {
+                bool fin;
+                if (EXACT) {
+                    exact_segment<COUNT, false>(S, M, rl.st, true, lm, pstk, wk);
+                    fin = true;
+                } else if (FF == 1 && rl.shadow) {
+                    exact_T_own<COUNT>(S, M, rl.st, lm, wk);
+                    fin = true;
+                } else {
+                    fin = track_own<COUNT>(S, M, rl.st, lm, wk);
+                }
+                if (fin && rl.segment_done(S, M, A)) more = next();
+            }
         }
     }
     if (valid) rl.result(A, out4);
@@ -939,7 +1352,7 @@ static __device__ void ratio_rays(const SceneView& S, const MaskView& M, const f
         if (valid) {
             Rng g;
             g.init(seed, (uint32_t)idx, (uint32_t)s, 1u);
-            begin_segment(S, st, r, r + 3, r[6], r[7], fixed_weights(M), MODE_RATIO, g);
+            begin_segment(S, st, r, r + 3, r[6], r[7], fixed_weights(M.cells, lm.cw), MODE_RATIO, M.lod2, g);
         }
         track_camera<COUNT>(S, M, st, valid, lm, pstk, wk);
         s1 += st.T;
@@ -965,10 +1378,9 @@ __global__ __launch_bounds__(TR_THREADS) void k_density(SceneView S, MaskView M,
     __shared__ int stk[TR_STACK * TR_THREADS];
     int i = blockIdx.x * TR_THREADS + threadIdx.x;
     if (i >= n) return;
-    CellW cw = fixed_weights(M);
     float x = pts[3 * (size_t)i], y = pts[3 * (size_t)i + 1], z = pts[3 * (size_t)i + 2];
     Work wk{};
-    kappa[i] = point_density<false>(S, M, cw, x, y, z, stk + threadIdx.x, wk);
+    kappa[i] = point_density<false>(S, M, x, y, z, stk + threadIdx.x, wk);
     if (kbar) {
         float kb = 0.0f;
         if (x >= S.glo[0] && x <= S.ghi[0] && y >= S.glo[1] && y <= S.ghi[1] && z >= S.glo[2] && z <= S.ghi[2]) {
@@ -976,7 +1388,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_density(SceneView S, MaskView M,
             int iy = min(S.G - 1, max(0, (int)floorf((y - S.glo[1]) * S.ginv[1])));
             int iz = min(S.G - 1, max(0, (int)floorf((z - S.glo[2]) * S.ginv[2])));
             float mw[GF_NCELLS];
-            for (int c = 0; c < GF_NCELLS; ++c) mw[c] = cw.mw(c);
+            for (int c = 0; c < GF_NCELLS; ++c) mw[c] = ((M.cells >> c) & 1u) ? 1.0f : 0.0f;
             kb = voxel_majorant(S, (iz * S.G + iy) * S.G + ix, mw);
         }
         kbar[i] = kb;
@@ -985,7 +1397,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_density(SceneView S, MaskView M,
 
 // The first 256 B of the workspace hold the launch's chunk counter (zeroed by
 // k_zero before the launch); the lanes' slices follow.
-#define WS_HEAD 64
+#define WS_HEAD GF_TRACK_HEAD_FLOATS
 
 __global__ void k_zero(unsigned* p) { *p = 0u; }
 
@@ -1007,7 +1419,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, c
     }
 }
 
-template <bool COUNT>
+template <bool COUNT, int FF>
 __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, const float* __restrict__ rays, int n,
                                                        int tile_w, int nchunks, RenderArgs A, float* __restrict__ ws,
                                                        float* __restrict__ Lm, float* __restrict__ Lv,
@@ -1019,7 +1431,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, 
     for (int c = next_chunk((unsigned*)ws); c < nchunks; c = next_chunk((unsigned*)ws)) {
         int idx = ray_of_tr(tile_order(c, nchunks, tile_w) * TR_THREADS + (int)threadIdx.x, n, tile_w);
         float o[4];
-        render_rays<COUNT>(S, M, A, rays, idx, lm, pstk, wk, o);
+        render_rays<COUNT, FF>(S, M, A, rays, idx, lm, pstk, wk, o);
         if (!COUNT && idx >= 0) {
             Lm[idx] = o[0];
             if (Lv) Lv[idx] = o[1];
@@ -1032,6 +1444,9 @@ __global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, 
         atomicAdd(counters + 1, wk.nodes);
         atomicAdd(counters + 2, wk.prims);
         atomicAdd(counters + 3, wk.windows);
+        atomicAdd(counters + 4, wk.used);
+        atomicAdd(counters + 5, wk.pq_nodes);
+        atomicAdd(counters + 6, wk.cover);
     }
 }
 
@@ -1065,7 +1480,7 @@ __global__ __launch_bounds__(TR_THREADS) void k_render_tiles(const ServeReq* __r
         int local = (c % chunks_per_tile) * TR_THREADS + (int)threadIdx.x;
         int idx = local < tl.count ? tl.first + local : -1;
         float o[4];
-        render_rays<false>(R.S, R.M, R.A, R.rays, idx, lm, pstk, wk, o);
+        render_rays<false, 0>(R.S, R.M, R.A, R.rays, idx, lm, pstk, wk, o);
         if (idx >= 0) R.out[idx] = o[0];
     }
 }
@@ -1083,18 +1498,30 @@ static unsigned tr_blocks(int64_t n, int tile_w) {
     return (unsigned)((tr_threads(n, tile_w) + TR_THREADS - 1) / TR_THREADS);
 }
 
+static RenderArgs render_args(const gf_render_desc* d) {
+    RenderArgs A;
+    A.spp = d->spp;
+    A.multiple = d->multiple;
+    A.max_scatter = d->max_scatter;
+    A.stochastic = d->stochastic;
+    A.exact = d->free_flight;
+    A.albedo = d->albedo;
+    A.hg = d->hg_g;
+    A.env = d->env;
+    A.strat.level = d->level_strategy;
+    A.strat.bin = d->bin_strategy;
+    A.strat.beta = d->beta;
+    A.strat.delta = d->delta;
+    A.shadow_cells = (uint32_t)(d->shadow_cells & 0xFFFu);
+    A.seed = d->seed;
+    return A;
+}
+
 gf_status gf_serve_fill_req(const gf_request* q, const float* rays, void* out_desc) {
     ServeReq* d = (ServeReq*)out_desc;
     d->S = gf_scene_view(q->scene);
     d->M = gf_mask_view(q->render.mask);
-    d->A.spp = q->render.spp;
-    d->A.multiple = q->render.multiple;
-    d->A.max_scatter = q->render.max_scatter;
-    d->A.stochastic = q->render.stochastic;
-    d->A.albedo = q->render.albedo;
-    d->A.hg = q->render.hg_g;
-    d->A.env = q->render.env;
-    d->A.seed = q->render.seed;
+    d->A = render_args(&q->render);
     d->rays = rays;
     d->out = q->out;
     d->n = q->camera.width * q->camera.height;
@@ -1155,7 +1582,7 @@ __global__ __launch_bounds__(256) void k_camera(gf_camera cam, float fx, float f
 // ---------------------------------------------------------------------------
 // host entry points
 // ---------------------------------------------------------------------------
-static gf_status check_depth(const gf_scene_s* s, const char* who) {
+gf_status gf_check_track_depth(const gf_scene_s* s, const char* who) {
     if (s->depth > TR_STACK) return gf_fail(GF_EINVAL, "%s: LBVH depth %d exceeds the point-query stack", who, s->depth);
     return GF_OK;
 }
@@ -1191,7 +1618,8 @@ extern "C" gf_status gf_density(gf_scene s, const float* pts, int64_t n, gf_mask
                                 void* stream) {
     if (!s || (n && (!pts || !kappa))) return gf_fail(GF_EINVAL, "gf_density: NULL argument");
     if (n < 0 || n > INT32_MAX / 3) return gf_fail(GF_EINVAL, "gf_density: n out of range");
-    gf_status st = check_depth(s, "gf_density");
+    if (kbar && s->G == 0) return gf_fail(GF_EINVAL, "gf_density: kbar needs a scene built with a majorant grid");
+    gf_status st = gf_check_track_depth(s, "gf_density");
     if (st != GF_OK || n == 0) return st;
     k_density<<<(unsigned)((n + TR_THREADS - 1) / TR_THREADS), TR_THREADS, 0, (hipStream_t)stream>>>(
         gf_scene_view(s), gf_mask_view(mask), pts, (int)n, kappa, kbar);
@@ -1204,7 +1632,8 @@ extern "C" gf_status gf_transmittance_ratio(gf_scene s, const float* rays, int64
     if (!s || (n && (!rays || !T_mean))) return gf_fail(GF_EINVAL, "gf_transmittance_ratio: NULL argument");
     if (spp < 1) return gf_fail(GF_EINVAL, "gf_transmittance_ratio: spp must be >= 1");
     gf_status st = check_rays_tr(n, image_width, "gf_transmittance_ratio");
-    if (st == GF_OK) st = check_depth(s, "gf_transmittance_ratio");
+    if (st == GF_OK) st = gf_check_track_depth(s, "gf_transmittance_ratio");
+    if (st == GF_OK && n > 0) st = gf_validate_rays(rays, n, (hipStream_t)stream, "gf_transmittance_ratio");
     if (st != GF_OK || n == 0) return st;
     unsigned nb = tr_blocks(n, image_width);
     Workspace ws;
@@ -1218,34 +1647,46 @@ extern "C" gf_status gf_transmittance_ratio(gf_scene s, const float* rays, int64
     return GF_OK;
 }
 
+// Launch of the render kernel over n rays with the tracking workspace ws
+// (gf_track_workspace_bytes(tr_blocks(n, image_width)) bytes).
+static gf_status render_launch(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
+                               float* ws, float* L_mean, float* L_var, float* T_mean, float* T_var, hipStream_t sm,
+                               unsigned long long* counters, unsigned max_waves = TR_RES_BLOCKS) {
+    const RenderArgs A = render_args(d);
+    const int ff = A.exact ? 2 : (d->transmittance ? 1 : 0);
+    if (ff) {
+        gf_status st = gf_ensure_weideman_track();
+        if (st != GF_OK) return st;
+    }
+    unsigned nb = tr_blocks(n, image_width);
+    int total = (int)nb;  // chunks of TR_THREADS rays
+    k_zero<<<1, 1, 0, sm>>>((unsigned*)ws);
+    const SceneView S = gf_scene_view(s);
+    const MaskView M = gf_mask_view(d->mask);
+    const unsigned g = std::min(res_blocks(nb), max_waves);
+    auto launch = [&](auto kernel, float* a, float* b, float* c, float* e, unsigned long long* cnt) {
+        kernel<<<g, TR_THREADS, 0, sm>>>(S, M, rays, (int)n, image_width, total, A, ws, a, b, c, e, cnt);
+    };
+    if (counters) {
+        if (ff == 0) launch(k_render<true, 0>, nullptr, nullptr, nullptr, nullptr, counters);
+        if (ff == 1) launch(k_render<true, 1>, nullptr, nullptr, nullptr, nullptr, counters);
+        if (ff == 2) launch(k_render<true, 2>, nullptr, nullptr, nullptr, nullptr, counters);
+    } else {
+        if (ff == 0) launch(k_render<false, 0>, L_mean, L_var, T_mean, T_var, nullptr);
+        if (ff == 1) launch(k_render<false, 1>, L_mean, L_var, T_mean, T_var, nullptr);
+        if (ff == 2) launch(k_render<false, 2>, L_mean, L_var, T_mean, T_var, nullptr);
+    }
+    GF_HIP(hipGetLastError());
+    return GF_OK;
+}
+
 gf_status gf_render_launch(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
                            float* L_mean, float* L_var, float* T_mean, float* T_var, hipStream_t sm,
                            unsigned long long* counters) {
-    RenderArgs A;
-    A.spp = d->spp;
-    A.multiple = d->multiple;
-    A.max_scatter = d->max_scatter;
-    A.stochastic = d->stochastic;
-    A.albedo = d->albedo;
-    A.hg = d->hg_g;
-    A.env = d->env;
-    A.seed = d->seed;
-    unsigned nb = tr_blocks(n, image_width);
     Workspace ws;
-    gf_status st = ws.alloc(nb, sm, "gf_render");
+    gf_status st = ws.alloc(tr_blocks(n, image_width), sm, "gf_render_rays");
     if (st != GF_OK) return st;
-    int total = (int)nb;  // chunks of TR_THREADS rays
-    k_zero<<<1, 1, 0, sm>>>((unsigned*)ws.p);
-    if (counters)
-        k_render<true><<<res_blocks(nb), TR_THREADS, 0, sm>>>(gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n,
-                                                              image_width, total, A, ws.p, nullptr, nullptr, nullptr,
-                                                              nullptr, counters);
-    else
-        k_render<false><<<res_blocks(nb), TR_THREADS, 0, sm>>>(gf_scene_view(s), gf_mask_view(d->mask), rays, (int)n,
-                                                               image_width, total, A, ws.p, L_mean, L_var, T_mean,
-                                                               T_var, nullptr);
-    GF_HIP(hipGetLastError());
-    return GF_OK;
+    return render_launch(s, rays, n, image_width, d, ws.p, L_mean, L_var, T_mean, T_var, sm, counters);
 }
 
 gf_status gf_check_render_desc(const gf_render_desc* d, const char* who) {
@@ -1253,31 +1694,95 @@ gf_status gf_check_render_desc(const gf_render_desc* d, const char* who) {
     if (d->spp < 1 || d->max_scatter < 0) return gf_fail(GF_EINVAL, "%s: spp >= 1 and max_scatter >= 0 required", who);
     if (!isfinite(d->albedo) || !isfinite(d->hg_g) || !(fabsf(d->hg_g) < 1.0f) || !isfinite(d->env))
         return gf_fail(GF_EINVAL, "%s: albedo / hg_g / env invalid", who);
+    if (d->stochastic) {
+        if (d->level_strategy < GF_LEVEL_ALL || d->level_strategy > GF_LEVEL_POWER_CV_ACCUM)
+            return gf_fail(GF_EINVAL, "%s: unknown level strategy %d", who, d->level_strategy);
+        if (d->bin_strategy < GF_BIN_ALL || d->bin_strategy > GF_BIN_MIXTURE)
+            return gf_fail(GF_EINVAL, "%s: unknown bin strategy %d", who, d->bin_strategy);
+        if (!(d->beta >= 0.0f && d->beta < 1.0f)) return gf_fail(GF_EINVAL, "%s: beta must lie in [0, 1)", who);
+        if (!(d->delta >= 0.0f && d->delta <= 1.0f)) return gf_fail(GF_EINVAL, "%s: delta must lie in [0, 1]", who);
+    }
+    if (d->free_flight != 0 && d->free_flight != 1) return gf_fail(GF_EINVAL, "%s: free_flight must be 0 or 1", who);
+    if (d->transmittance != 0 && d->transmittance != 1)
+        return gf_fail(GF_EINVAL, "%s: transmittance must be 0 or 1", who);
+    if (!(d->mask.lod_k >= 0.0f) || !isfinite(d->mask.lod_k)) return gf_fail(GF_EINVAL, "%s: lod_k must be >= 0", who);
     return GF_OK;
 }
 
-extern "C" gf_status gf_render(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
-                               float* L_mean, float* L_var, float* T_mean, float* T_var, void* stream) {
-    if (!s || (n && (!rays || !L_mean))) return gf_fail(GF_EINVAL, "gf_render: NULL argument");
-    gf_status st = gf_check_render_desc(d, "gf_render");
-    if (st == GF_OK) st = check_rays_tr(n, image_width, "gf_render");
-    if (st == GF_OK) st = check_depth(s, "gf_render");
+// Argument checks shared by the ray-list render calls.
+static gf_status check_render_rays(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
+                                   hipStream_t sm, const char* who) {
+    gf_status st = gf_check_render_desc(d, who);
+    if (st == GF_OK) st = check_rays_tr(n, image_width, who);
+    if (st == GF_OK) st = gf_check_track_depth(s, who);
+    if (st == GF_OK && n > 0) st = gf_validate_rays(rays, n, sm, who);
+    return st;
+}
+
+extern "C" gf_status gf_render_rays(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
+                                    float* L_mean, float* L_var, float* T_mean, float* T_var, void* stream) {
+    if (!s || (n && (!rays || !L_mean))) return gf_fail(GF_EINVAL, "gf_render_rays: NULL argument");
+    hipStream_t sm = (hipStream_t)stream;
+    gf_status st = check_render_rays(s, rays, n, image_width, d, sm, "gf_render_rays");
     if (st != GF_OK || n == 0) return st;
-    return gf_render_launch(s, rays, n, image_width, d, L_mean, L_var, T_mean, T_var, (hipStream_t)stream, nullptr);
+    return gf_render_launch(s, rays, n, image_width, d, L_mean, L_var, T_mean, T_var, sm, nullptr);
 }
 
 extern "C" gf_status gf_render_counts(gf_scene s, const float* rays, int64_t n, int image_width,
                                       const gf_render_desc* d, uint64_t* counts, void* stream) {
     if (!s || !counts || (n && !rays)) return gf_fail(GF_EINVAL, "gf_render_counts: NULL argument");
-    gf_status st = gf_check_render_desc(d, "gf_render_counts");
-    if (st == GF_OK) st = check_rays_tr(n, image_width, "gf_render_counts");
-    if (st == GF_OK) st = check_depth(s, "gf_render_counts");
-    if (st != GF_OK) return st;
     hipStream_t sm = (hipStream_t)stream;
-    GF_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(uint64_t), sm));
-    if (n == 0) return GF_OK;
+    gf_status st = check_render_rays(s, rays, n, image_width, d, sm, "gf_render_counts");
+    if (st != GF_OK) return st;
+    st = gf_zero_words(counts, 2 * GF_RENDER_COUNTS, sm);
+    if (st != GF_OK || n == 0) return st;
     return gf_render_launch(s, rays, n, image_width, d, nullptr, nullptr, nullptr, nullptr, sm,
                             (unsigned long long*)counts);
+}
+
+// Camera render: the caller's workspace holds the camera rays (n x 32 B,
+// 256-byte aligned) followed by the tracking workspace.
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static gf_status camera_render_bytes(const gf_camera* cam, size_t* rays_bytes, size_t* total) {
+    const int64_t n = (int64_t)cam->width * cam->height;
+    const int tile_w = cam->width % 8 == 0 ? cam->width : 0;
+    *rays_bytes = align256((size_t)n * 8 * sizeof(float));
+    *total = *rays_bytes + align256(gf_track_workspace_bytes(tr_blocks(n, tile_w)));
+    return GF_OK;
+}
+
+extern "C" gf_status gf_render_workspace_size(gf_scene s, const gf_camera* cam, const gf_render_desc* d,
+                                              size_t* bytes) {
+    gf_status st = gf_check_camera(cam, "gf_render_workspace_size");
+    if (st == GF_OK) st = gf_check_render_desc(d, "gf_render_workspace_size");
+    if (st != GF_OK) return st;
+    if (!s || !bytes) return gf_fail(GF_EINVAL, "gf_render_workspace_size: NULL argument");
+    size_t rb;
+    return camera_render_bytes(cam, &rb, bytes);
+}
+
+extern "C" gf_status gf_render(gf_scene s, const gf_camera* cam, const gf_render_desc* d, void* workspace,
+                               size_t ws_bytes, float* radiance, float* primary_T, void* stream) {
+    gf_status st = gf_check_camera(cam, "gf_render");
+    if (st == GF_OK) st = gf_check_render_desc(d, "gf_render");
+    if (st != GF_OK) return st;
+    if (!s || !workspace || !radiance) return gf_fail(GF_EINVAL, "gf_render: NULL argument");
+    st = gf_check_track_depth(s, "gf_render");
+    if (st != GF_OK) return st;
+    if (((uintptr_t)workspace & 255u) != 0) return gf_fail(GF_EINVAL, "gf_render: workspace must be 256-byte aligned");
+    size_t rb, need;
+    camera_render_bytes(cam, &rb, &need);
+    if (ws_bytes < need)
+        return gf_fail(GF_EINVAL, "gf_render: workspace of %zu bytes, %zu needed", ws_bytes, need);
+    hipStream_t sm = (hipStream_t)stream;
+    const int64_t n = (int64_t)cam->width * cam->height;
+    const int tile_w = cam->width % 8 == 0 ? cam->width : 0;
+    float* rays = (float*)workspace;
+    st = gf_camera_launch(cam, rays, sm);
+    if (st != GF_OK) return st;
+    return render_launch(s, rays, n, tile_w, d, (float*)((char*)workspace + rb), radiance, nullptr, primary_T,
+                         nullptr, sm, nullptr);
 }
 
 gf_status gf_camera_launch(const gf_camera* cam, float* rays, hipStream_t sm) {
@@ -1324,4 +1829,9 @@ extern "C" gf_status gf_camera_rays(const gf_camera* cam, float* rays, void* str
     if (st != GF_OK) return st;
     if (!rays) return gf_fail(GF_EINVAL, "gf_camera_rays: NULL rays");
     return gf_camera_launch(cam, rays, (hipStream_t)stream);
+}
+
+gf_status gf_render_launch_in(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
+                              float* ws, float* radiance, float* primary_T, hipStream_t sm, unsigned max_waves) {
+    return render_launch(s, rays, n, image_width, d, ws, radiance, nullptr, primary_T, nullptr, sm, nullptr, max_waves);
 }

@@ -3,7 +3,7 @@ continuous-batching server and against the plain per-request renderer, and
 reports per-request latency (arrival -> result on the host).
 
 Only orchestration lives here: ray generation and rendering run in the HIP
-library (gf_camera_rays / gf_render / gf_server_*).
+library (gf_render / gf_server_*).
 """
 from __future__ import annotations
 
@@ -74,6 +74,9 @@ def run_plain(scenes, reqs, arrivals, outputs=None, time_limit=None, on_done=Non
     """FIFO plain renderer: each request rendered alone, in arrival order.
     on_done(k, seconds) is called as request k completes."""
     outs = outputs if outputs is not None else [torch.empty(r["res"] * r["res"], device="cuda") for r in reqs]
+    # one workspace of the largest size any request needs, allocated up front
+    need = max(_lib.gf_render_workspace_size(scenes[r["scene"]], request_camera(r), request_desc(r)) for r in reqs)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat = []
@@ -81,9 +84,8 @@ def run_plain(scenes, reqs, arrivals, outputs=None, time_limit=None, on_done=Non
         now = time.perf_counter() - t0
         if arrivals[k] > now:
             time.sleep(arrivals[k] - now)
-        rays = _lib.gf_camera_rays(request_camera(r))
-        L, _, _, _ = _lib.gf_render(scenes[r["scene"]], rays, request_desc(r), want_var=False)
-        outs[k].copy_(L)
+        L, _ = _lib.gf_render(scenes[r["scene"]], request_camera(r), request_desc(r), ws, want_T=False)
+        outs[k].copy_(L.view(-1))
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0 - arrivals[k])
         if on_done:

@@ -1,6 +1,7 @@
 """GPU checks of the continuous-batching server: every request completes,
 each image is bitwise the same rendered in the mix, alone through the server,
-and by the plain renderer (gf_camera_rays + gf_render); admission never holds
+by the plain camera renderer (gf_render, caller workspace) and through the
+ray-list call (gf_render_rays); admission never holds
 more device memory than the budget; requests that can never fit are
 rejected."""
 import numpy as np
@@ -37,9 +38,14 @@ def test_server_mix_equals_alone_and_plain():
         alone = serve.run_server(scenes, [r], np.zeros(1), mem_budget=budget, tile_rays=512, max_tiles=8,
                                  time_limit=60)[2][0]
         assert torch.equal(mix[k], alone), k
-        rays = gf.gf_camera_rays(serve.request_camera(r))
-        plain, _, _, _ = gf.gf_render(scenes[r["scene"]], rays, serve.request_desc(r))
-        assert torch.equal(mix[k], plain), k
+        cam, desc = serve.request_camera(r), serve.request_desc(r)
+        ws = torch.empty(gf.gf_render_workspace_size(scenes[r["scene"]], cam, desc), dtype=torch.uint8,
+                         device="cuda")
+        plain, _ = gf.gf_render(scenes[r["scene"]], cam, desc, ws)
+        assert torch.equal(mix[k], plain.view(-1)), k
+        rays = gf.gf_camera_rays(cam)
+        listed, _, _, _ = gf.gf_render_rays(scenes[r["scene"]], rays, desc)
+        assert torch.equal(mix[k], listed), k
         assert torch.isfinite(mix[k]).all()
 
 

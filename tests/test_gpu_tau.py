@@ -144,3 +144,37 @@ def test_counts_match_oracle_traversal():
     # chord tests agree except at tangency; box tests except at grazing
     assert np.abs(hits - oh).sum() <= 1e-4 * oh.sum() + 2
     assert np.abs(nodes - on).sum() <= 1e-3 * on.sum() + 2
+
+
+def _clamp_eps(params, rho, share=0.5):
+    """the eps at which about `share` of the primitives get a radius below 3"""
+    p = params.astype(np.float64)
+    arg = rho * np.abs(p[:, 14]) * p[:, 7:10].max(axis=1) / (2 * np.pi * p[:, 7] * p[:, 8] * p[:, 9])
+    return float(np.float32(np.quantile(arg, 1.0 - share) / math.exp(4.5)))
+
+
+@pytest.mark.parametrize("name", ["tiny256", "blob3000"])
+def test_adaptive_clamping(name):
+    """Adaptive clamping (a scene option): per-primitive radii min(3, E_i)
+    give a bit-exact LBVH (clamped leaf boxes) and optical depth to the D9
+    bar, both against the oracle under the same eps; fewer hits than at
+    r = 3."""
+    gf = require_gpu()
+    params = W.scene("tiny256") if name == "tiny256" else gen.blob_scene(3000, 5)
+    rho = float(np.float32(W.rho("tiny256") if name == "tiny256" else 0.004))
+    eps = _clamp_eps(params, rho)
+    radii = oracle.clamp_radii(params, rho, eps)
+    assert np.mean(radii < 3.0) > 0.3
+    scene = gf.Scene(dev(params), rho=rho, clamp_eps=eps)
+    got = {k: host(v) for k, v in gf.gf_scene_export_lbvh(scene).items()}
+    ref = oracle.lbvh(params, rho=rho, clamp_eps=eps)
+    for k in ("keys", "perm", "left", "right", "parent", "cellor"):
+        assert np.array_equal(got[k].view(ref[k].dtype), ref[k]), k
+    assert np.array_equal(got["aabb"].view(np.uint32), ref["aabb"].view(np.uint32))
+    rays = W.rays("tiny256") if name == "tiny256" else gen.pinhole_rays(64, 64)
+    tau, _ = gf.gf_optical_depth(scene, dev(rays), image_width=64)
+    rt, ab, hits = oracle.tau(params, rays, rho=rho, clamp_eps=eps)
+    _check_tau(host(tau), rt, ab, hits)
+    _, _, hits3 = oracle.tau(params, rays, rho=rho)
+    assert hits.sum() < hits3.sum()
+    assert scene.info().clamp_eps == np.float32(eps)

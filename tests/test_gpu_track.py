@@ -13,6 +13,7 @@ import gen
 import oracle
 from gen import workloads as W
 from gpu_util import dev, host, require_gpu
+from strategy_tables import enumerate_outcomes, expected_T
 
 pytestmark = pytest.mark.gpu
 
@@ -24,19 +25,25 @@ def _pooled(a, b, se):
 
 def _check_ratio(Tm, Tv, tau, spp, min_ok):
     """Ratio-tracking means against exp(-tau).  Deep rays (spp exp(-tau) < 5)
-    end at zero in nearly every sample, so their sample variance is no
-    standard error: they only get an absolute bound."""
-    ok = spp * np.exp(-tau) >= 5.0
+    are products of many factors whose mean comes from rare samples that a
+    run of this length rarely draws, so their sample variance is no standard
+    error: they get a bound relative to exp(-tau) instead (within five
+    standard errors plus ten times exp(-tau), and not negative beyond five
+    standard errors); the closed-form transmittance of the CDF-inversion
+    render pins deep rays exactly (test_gpu_strategies.py)."""
+    T = np.exp(-tau)
+    ok = spp * T >= 5.0
     assert ok.sum() >= min_ok
-    pooled, worst = _pooled(Tm[ok], np.exp(-tau[ok]), np.sqrt(Tv[ok] / spp))
+    pooled, worst = _pooled(Tm[ok], T[ok], np.sqrt(Tv[ok] / spp))
     assert pooled < 3.0 and worst < 5.0
-    assert np.all(np.abs(Tm[~ok] - np.exp(-tau[~ok])) < 2e-3)
+    se = np.sqrt(Tv[~ok] / spp)
+    assert np.all(np.abs(Tm[~ok] - T[~ok]) <= 5.0 * se + 10.0 * T[~ok])
 
 
 def test_density_and_majorant():
     gf = require_gpu()
     params, rho = W.scene("tiny256"), W.rho("tiny256")
-    scene = gf.Scene(dev(params), rho=rho)
+    scene = gf.Scene(dev(params), rho=rho, majorant_grid=64)
     g = np.random.default_rng(0)
     pts = np.concatenate([params[g.choice(256, 3000), 0:3] + g.normal(0, 0.05, (3000, 3)),
                           g.uniform(-0.1, 1.1, (1000, 3))]).astype(np.float32)
@@ -86,7 +93,7 @@ def _render_pair(params, rays, rho, spp_gpu, spp_orc, **kw):
     gf = require_gpu()
     scene = gf.Scene(dev(params), rho=rho)
     d = gf.render_desc(spp=spp_gpu, seed=5, **kw)
-    Lm, Lv, Tm, Tv = (host(x) for x in gf.gf_render(scene, dev(rays), d))
+    Lm, Lv, Tm, Tv = (host(x) for x in gf.gf_render_rays(scene, dev(rays), d))
     oL, oLv, oT, oTv = oracle.render(params, rays, spp_orc, seed=9, rho=rho, **kw)
     return (Lm, Lv / spp_gpu), (oL, oLv / spp_orc), (Tm, Tv / spp_gpu), (oT, oTv / spp_orc)
 
@@ -117,7 +124,7 @@ def test_furnace_positive_density_exact():
     scene = gf.Scene(dev(params), rho=0.05)
     rays = gen.ortho_rays(16, 16)
     d = gf.render_desc(spp=8, multiple=True, max_scatter=1 << 30, albedo=1.0, hg_g=0.3, seed=1)
-    L, _, _, _ = gf.gf_render(scene, dev(rays), d)
+    L, _, _, _ = gf.gf_render_rays(scene, dev(rays), d)
     assert torch.all(L == 1.0)
 
 
@@ -129,24 +136,15 @@ def test_stochastic_primary_transmittance_exact_expectation():
     rays = gen.random_rays(48, 12)
     scene = gf.Scene(dev(params), rho=rho)
     spp = 20000
-    d = gf.render_desc(spp=spp, multiple=True, albedo=0.9, hg_g=0.3, stochastic=True, seed=21)
-    _, _, Tm, Tv = (host(x) for x in gf.gf_render(scene, dev(rays), d))
-    info = scene.info()
-    med = np.array(info.cell_median_kw[:], dtype=np.float64)
+    d = gf.render_desc(spp=spp, multiple=True, albedo=0.9, hg_g=0.3, stochastic=True, seed=21, bin="mixture")
+    _, _, Tm, Tv = (host(x) for x in gf.gf_render_rays(scene, dev(rays), d))
+    med = oracle.cell_medians(params)
+    tcs = np.stack([oracle.tau(params, rays, rho=rho, cells=1 << c)[0] for c in range(12)], axis=1)
     exact, keep = [], []
-    for ray in rays:
-        tc = [oracle.tau(params, ray[None, :], rho=rho, cells=1 << c)[0][0] for c in range(12)]
-        v = ray[3:6] / np.linalg.norm(ray[3:6])
-        e, mx = 0.0, 0.0
-        for l in (1, 2, 3):
-            w = np.exp(-0.5 * med[3 * l:3 * l + 3] ** 2 * np.abs(v) ** 2)
-            p = 0.5 * w / w.sum() + 1.0 / 6.0
-            for k in range(3):
-                t = sum(tc[0:3]) + 3 / p[k] * tc[3 * l + k]
-                e += p[k] / 3 * math.exp(-t)
-                mx = max(mx, abs(t))
-        exact.append(e)
-        keep.append(mx < 0.6)
+    for ray, tc in zip(rays, tcs):
+        out = enumerate_outcomes("uniform_cv", "mixture", med, ray[3:6])
+        exact.append(expected_T(out, tc))
+        keep.append(max(abs(float(np.dot(w, tc))) for _, w in out) < 0.6)
     exact, keep = np.array(exact), np.array(keep)
     pooled, worst = _pooled(Tm[keep], exact[keep], np.sqrt(Tv[keep] / spp))
     assert pooled < 3.0 and worst < 5.0
@@ -158,12 +156,17 @@ def test_render_deterministic_and_batch_independent():
     scene = gf.Scene(dev(params), rho=rho)
     rays = dev(gen.pinhole_rays(64, 64))
     d = gf.render_desc(spp=2, multiple=True, albedo=0.9, hg_g=0.3, stochastic=True, seed=7)
-    a = gf.gf_render(scene, rays, d, image_width=64)[0]
-    b = gf.gf_render(scene, rays, d, image_width=0)[0]
-    c = gf.gf_render(scene, rays[1000:1100].contiguous(), d)[0]
+    a = gf.gf_render_rays(scene, rays, d, image_width=64)[0]
+    b = gf.gf_render_rays(scene, rays, d, image_width=0)[0]
     assert torch.equal(a, b)
-    # a ray's result depends only on its own index in the batch: compare the
-    # sub-batch against rays traced at the same indices
+    # a ray's result depends only on its own index in the launch: rays
+    # 1000..1099 kept at their indices, every other ray replaced (reversed
+    # order, a different camera), give the same bits
+    other = dev(gen.pinhole_rays(64, 64, eye=(1.9, 0.4, -0.8)))[torch.arange(4095, -1, -1, device="cuda")]
+    other[1000:1100] = rays[1000:1100]
+    c = gf.gf_render_rays(scene, other.contiguous(), d)[0]
+    assert torch.equal(a[1000:1100], c[1000:1100])
+    assert not torch.equal(a[:1000], c[:1000])
     assert torch.isfinite(a).all() and torch.isfinite(c).all()
 
 
@@ -180,7 +183,7 @@ def test_render_full_size_sampled_blob100k():
     Lsum, Lv_sum = np.zeros(len(sub)), np.zeros(len(sub))
     for seed in range(runs):
         d = gf.render_desc(spp=8, multiple=False, albedo=0.9, seed=1234 + seed)
-        L, Lv, _, _ = gf.gf_render(scene, drays, d, image_width=512)
+        L, Lv, _, _ = gf.gf_render_rays(scene, drays, d, image_width=512)
         Lsum += host(L)[sub]
         Lv_sum += host(Lv)[sub]
         print("launch", seed, "done", flush=True)
@@ -195,22 +198,13 @@ def test_render_full_size_sampled_blob100k():
     assert pooled < 3.0 and worst < 6.0
 
 
-def _stochastic_expectation(params, rays, rho, med):
+def _stochastic_expectation(params, rays, rho, level, bin):
     """E[T_hat] of the stochastic primary transmittance, summed exactly over
-    the per-segment mask distribution: level 0 always, level l in 1..3 with
-    probability 1/3, bin k with p_k = w_k/(2W) + 1/6 and weight 3/p_k."""
+    the per-segment mask distribution (enumerated from the strategy tables
+    with the oracle's cell medians and per-cell optical depths)."""
+    med = oracle.cell_medians(params)
     tcs = np.stack([oracle.tau(params, rays, rho=rho, cells=1 << c)[0] for c in range(12)], axis=1)
-    out = []
-    for ray, tc in zip(rays, tcs):
-        v = ray[3:6] / np.linalg.norm(ray[3:6])
-        e = 0.0
-        for l in (1, 2, 3):
-            w = np.exp(-0.5 * med[3 * l:3 * l + 3] ** 2 * np.abs(v) ** 2)
-            p = 0.5 * w / w.sum() + 1.0 / 6.0
-            for k in range(3):
-                e += p[k] / 3 * math.exp(-(sum(tc[0:3]) + 3 / p[k] * tc[3 * l + k]))
-        out.append(e)
-    return np.array(out)
+    return np.array([expected_T(enumerate_outcomes(level, bin, med, ray[3:6]), tc) for ray, tc in zip(rays, tcs)])
 
 
 def test_render_full_size_multiple_stochastic_blob1m():
@@ -223,8 +217,9 @@ def test_render_full_size_multiple_stochastic_blob1m():
     params, rays, rho = W.scene("blob1m"), W.rays("blob1m"), W.rho("blob1m")
     scene = gf.Scene(dev(params), rho=rho)
     band = rays[496 * 1024:528 * 1024]
-    d = gf.render_desc(spp=4, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, stochastic=True, seed=41)
-    L, Lv, T, Tv = (host(x) for x in gf.gf_render(scene, dev(band), d, image_width=1024))
+    d = gf.render_desc(spp=4, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, stochastic=True, seed=41,
+                       bin="mixture")
+    L, Lv, T, Tv = (host(x) for x in gf.gf_render_rays(scene, dev(band), d, image_width=1024))
     print("band done: mean L %.4f, mean T %.4f" % (L.mean(), T.mean()), flush=True)
     assert np.all(np.isfinite(L)) and np.all(np.isfinite(T))
     assert np.all(np.isfinite(Lv)) and np.all(np.isfinite(Tv))
@@ -234,20 +229,31 @@ def test_render_full_size_multiple_stochastic_blob1m():
     sub = W.pixel_subset(band.shape[0], k=24, seed=23)
     rs = band[sub]
     copies = 512
-    d = gf.render_desc(spp=4, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, stochastic=True, seed=43)
-    _, _, Tc, _ = (host(x) for x in gf.gf_render(scene, dev(np.repeat(rs, copies, axis=0)), d))
+    d = gf.render_desc(spp=4, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, stochastic=True, seed=43,
+                       bin="mixture")
+    Lc, _, Tc, _ = (host(x) for x in gf.gf_render_rays(scene, dev(np.repeat(rs, copies, axis=0)), d))
     Tc = Tc.reshape(len(rs), copies)
     spp = 4 * copies
     Tm, Tv = Tc.mean(axis=1), Tc.var(axis=1, ddof=1) * 4
     print("sampled pixels done", flush=True)
-    med = np.array(scene.info().cell_median_kw[:], dtype=np.float64)
-    exact = _stochastic_expectation(params, rs, rho, med)
+    exact = _stochastic_expectation(params, rs, rho, "uniform_cv", "mixture")
     ok = spp * exact >= 5.0
     assert ok.sum() >= 8
     pooled, worst = _pooled(Tm[ok], exact[ok], np.sqrt(Tv[ok] / spp))
-    print("pooled %.2f worst %.2f over %d pixels" % (pooled, worst, ok.sum()), flush=True)
+    print("primary T: pooled %.2f worst %.2f over %d pixels" % (pooled, worst, ok.sum()), flush=True)
     assert pooled < 3.0 and worst < 5.0
-    assert np.all(np.abs(Tm[~ok] - exact[~ok]) < 2e-3)
+    se = np.sqrt(Tv[~ok] / spp)
+    assert np.all(np.abs(Tm[~ok] - exact[~ok]) <= 5.0 * se + 10.0 * exact[~ok])
+    # the workload's output, radiance, against the oracle's own render of
+    # the same pixels with the same strategies (both Monte Carlo: in mean)
+    Lc = Lc.reshape(len(rs), copies)
+    gL, gLv = Lc.mean(axis=1), Lc.var(axis=1, ddof=1) * 4 / spp
+    spp_o = 128
+    oL, oLv, _, _ = oracle.render(params, rs, spp_o, seed=8, rho=rho, multiple=True, max_scatter=16, albedo=0.9,
+                                  hg_g=0.3, stochastic=True, level="uniform_cv", bin="mixture")
+    pooled, worst = _pooled(gL, oL, np.sqrt(gLv + oLv / spp_o))
+    print("radiance: pooled %.2f worst %.2f" % (pooled, worst), flush=True)
+    assert pooled < 3.0 and worst < 6.0
 
 
 def test_render_edge_cases():
@@ -270,16 +276,16 @@ def test_render_edge_cases():
     rays[5:7, 7] = np.inf
     for multiple in (False, True):
         d = gf.render_desc(spp=4, multiple=multiple, albedo=0.9, hg_g=0.3, seed=13)
-        L, Lv, T, Tv = (host(x) for x in gf.gf_render(scene, dev(rays), d))
+        L, Lv, T, Tv = (host(x) for x in gf.gf_render_rays(scene, dev(rays), d))
         assert np.all(L[:5] == 1.0) and np.all(T[:5] == 1.0)
         assert np.all(Lv[:5] == 0.0) and np.all(Tv[:5] == 0.0)
         assert np.all(np.isfinite(L)) and np.all(np.isfinite(T))
-        L1, _, T1, _ = (host(x) for x in gf.gf_render(scene, dev(rays[6:7]), d))
+        L1, _, T1, _ = (host(x) for x in gf.gf_render_rays(scene, dev(rays[6:7]), d))
         # the ray's streams are keyed by its index: index 6 in the ragged
         # launch is index 0 alone, so compare the launch with itself shifted
         shifted = np.concatenate([rays[6:7], rays[:6]])
-        L2, _, T2, _ = (host(x) for x in gf.gf_render(scene, dev(shifted), d))
+        L2, _, T2, _ = (host(x) for x in gf.gf_render_rays(scene, dev(shifted), d))
         assert L1[0] == L2[0] and T1[0] == T2[0]
         d0 = gf.render_desc(spp=4, multiple=multiple, albedo=0.9, hg_g=0.3, seed=13, mask=gf.make_mask(0))
-        L0, _, T0, _ = (host(x) for x in gf.gf_render(scene, dev(rays), d0))
+        L0, _, T0, _ = (host(x) for x in gf.gf_render_rays(scene, dev(rays), d0))
         assert np.all(L0 == 1.0) and np.all(T0 == 1.0)

@@ -49,3 +49,43 @@ def test_null_arguments_rejected_without_device(so):
     out = ctypes.c_void_p()
     assert so.gf_scene_create(None, ctypes.c_int64(10), None, None, ctypes.byref(out)) == -1
     assert b"NULL" in so.gf_last_error()
+
+
+def _desc(**kw):
+    from paper_2602_05081_amd import _lib
+    d = _lib.render_desc(spp=2, stochastic=True)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("field,value,msg", [("level_strategy", 9, b"level strategy"),
+                                             ("bin_strategy", -1, b"bin strategy"),
+                                             ("beta", 1.0, b"beta"), ("delta", 1.5, b"delta"),
+                                             ("free_flight", 2, b"free_flight"), ("spp", 0, b"spp")])
+def test_render_description_validated_on_the_host(so, field, value, msg):
+    """An invalid render description is rejected by the size query and by
+    the camera render before anything touches a device."""
+    from paper_2602_05081_amd import _lib
+    L = _lib.lib()
+    cam = _lib.camera(1, width=16, height=16)
+    d = _desc(**{field: value})
+    size = ctypes.c_size_t()
+    assert L.gf_render_workspace_size(None, ctypes.byref(cam), ctypes.byref(d), ctypes.byref(size)) == -1
+    assert msg in L.gf_last_error()
+    assert L.gf_render(None, ctypes.byref(cam), ctypes.byref(d), None, 0, None, None, None) == -1
+    assert msg in L.gf_last_error()
+
+
+def test_render_camera_validated_on_the_host(so):
+    from paper_2602_05081_amd import _lib
+    L = _lib.lib()
+    d = _desc()
+    size = ctypes.c_size_t()
+    for cam in (_lib.camera(1, width=0, height=16), _lib.camera(3, width=8, height=8),
+                _lib.camera(1, eye=(0.5, 0.5, 0.5), target=(0.5, 0.5, 0.5))):
+        assert L.gf_render_workspace_size(None, ctypes.byref(cam), ctypes.byref(d), ctypes.byref(size)) == -1
+    # a valid description and camera with no scene: NULL argument
+    cam = _lib.camera(1, width=16, height=16)
+    assert L.gf_render_workspace_size(None, ctypes.byref(cam), ctypes.byref(d), ctypes.byref(size)) == -1
+    assert b"NULL" in L.gf_last_error()

@@ -1,5 +1,5 @@
 """Pins of the level / bin partition, the cone mask and the per-cell medians
-of |k_W| (Sec. 4.5 implementation details; the stochastic strategies that
+of |k_W| (Sec. 4.6 implementation details; the stochastic strategies that
 use them are pinned in test_oracle_strategies.py)."""
 import math
 
