@@ -379,7 +379,9 @@ __global__ __launch_bounds__(256) void k_leaves(const float* __restrict__ params
             for (int k = 0; k < 3; ++k) acc += R[a][k] * R[b][k] / (s[k] * s[k]);
             A[idx++] = acc;
         }
-    for (int k = 0; k < 6; ++k) A64[(size_t)j * 6 + k] = A[k];
+    for (int k = 0; k < 6; ++k) A64[(size_t)j * GF_A64 + k] = A[k];
+    A64[(size_t)j * GF_A64 + 6] = rr * rr;
+    A64[(size_t)j * GF_A64 + 7] = 0.0;
     double amp = (double)rho * (double)p[14] / (4.0 * GF_PI * s[0] * s[1] * s[2]);
     float4* rec = prims + (size_t)j * 4;
     rec[0] = make_float4(p[0], p[1], p[2], p[13]);
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(256) void k_grid_splat(const float* __restrict__ pa
     int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const float* p = params + (size_t)perm[j] * 15;
-    int cell = __float_as_int(prims[(size_t)j * 4 + 3].z);
+    int cell = rec_cell(prims[(size_t)j * 4 + 3].w);
     float smax = fmaxf(p[7], fmaxf(p[8], p[9]));
     double c = (double)rho * fabs((double)p[14]) / (pow(2.0 * GF_PI, 1.5) * (double)p[7] * p[8] * p[9]);
     double R[3][3], qh[4];
@@ -630,7 +632,7 @@ extern "C" gf_status gf_scene_create(const float* params, int64_t n, const gf_sc
     size_t total = 0;
     GF_TRY(dalloc(&s->prims, (size_t)n * 4, &total));
     GF_TRY(dalloc(&s->aux, (size_t)n * 3, &total));
-    GF_TRY(dalloc(&s->A64, (size_t)n * 6, &total));
+    GF_TRY(dalloc(&s->A64, (size_t)n * GF_A64, &total));
     GF_TRY(dalloc(&s->nodes, (size_t)std::max<int64_t>(n - 1, 1), &total));
     GF_TRY(dalloc(&s->cnodes, (size_t)std::max<int64_t>(n - 1, 1), &total));
     GF_TRY(dalloc(&s->grid, (size_t)G * G * G * GF_NCELLS, &total));

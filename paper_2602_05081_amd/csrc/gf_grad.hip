@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_tau_bwd(SceneView S, MaskView M, const 
 #pragma unroll
         for (int k = 0; k < 15; ++k) g[k] = 0.0f;
         HitGeom H;
-        bool hit = active && hit_geom(P, R, P.r2, S.A64 + (size_t)j * 6, H) && lod_keep64(P, R, H, M.lod_k);
+        bool hit = active && hit_geom(P, R, S.A64 + (size_t)j * GF_A64, H) && lod_keep64(P, R, H, M.lod_k);
         if (hit) hit_grad(P, S.aux + (size_t)j * 3, H, R, P.r2, gr, g);
         if (!__ballot(hit)) return;
         float* dst = dparams + (size_t)P.orig * 15;

@@ -110,7 +110,7 @@ struct HitGeom {
 // Geometry from A (a00 a01 a02 a11 a12 a22).  Returns 0 when the clipped
 // chord is empty, 1 on a hit, 2 (float32 path only) when h^2 lies within
 // [r^2 - 0.05, r^2 + 0.01) and must be redone with binary64 A.
-static __device__ __forceinline__ int hit_geom_a(const PrimF& P, const RayD& R, float r2, const double* A,
+static __device__ __forceinline__ int hit_geom_a(const PrimF& P, const RayD& R, double r2, const double* A,
                                                  bool h2_double, HitGeom& H) {
     double dx = R.ox - P.mux, dy = R.oy - P.muy, dz = R.oz - P.muz;
     double avx = A[0] * R.vx + A[1] * R.vy + A[2] * R.vz;
@@ -165,12 +165,13 @@ static __device__ __forceinline__ int hit_geom_a(const PrimF& P, const RayD& R, 
     return 1;
 }
 
-// Chord geometry of one hit from the binary64 Sigma^-1 of primitive j;
-// false when the clipped chord is empty.
-static __device__ __forceinline__ bool hit_geom(const PrimF& P, const RayD& R, float r2,
-                                                const double* __restrict__ A64j, HitGeom& H) {
+// Chord geometry of one hit from the binary64 record of primitive j
+// (Sigma^-1 and the squared truncation radius); false when the clipped
+// chord is empty.
+static __device__ __forceinline__ bool hit_geom(const PrimF& P, const RayD& R, const double* __restrict__ A64j,
+                                                HitGeom& H) {
     double A[6] = {A64j[0], A64j[1], A64j[2], A64j[3], A64j[4], A64j[5]};
-    return hit_geom_a(P, R, r2, A, true, H) == 1;
+    return hit_geom_a(P, R, A64j[6], A, true, H) == 1;
 }
 
 // Continuous LOD in binary64 (supplementary "LOD Selection"): primitive P

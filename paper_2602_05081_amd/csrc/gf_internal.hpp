@@ -16,7 +16,8 @@
 //            primitives collapsed into a leaf range: c < 0 is the Morton
 //            range first = ~c & 0x0FFFFFFF, count = (~c >> 28) + 1 (the
 //            subtree's primitives are contiguous in Morton order).
-//   A64    : n x 48 B, Sigma^-1 in binary64 for the chord geometry of the
+//   A64    : n x 64 B, Sigma^-1 (6) and the squared truncation radius in
+//            binary64 (one pad) for the chord geometry of the
 //            optical-depth and adjoint kernels (float32 rounding of an
 //            anisotropic Sigma^-1 moves h^2 by ~1e-5 relative).
 //   grid   : G^3 voxels x 12 cells of float32 majorants over the root box.
@@ -32,6 +33,7 @@
 #define GF_NCELLS 12
 #define GF_STACK 128
 #define GF_LEAF_MAX 4
+#define GF_A64 8  // binary64 words per primitive in SceneView::A64
 
 // last word of a primitive record: caller index in the low 28 bits, cell above
 static __device__ __forceinline__ int rec_orig(float w) { return __float_as_int(w) & 0x0FFFFFFF; }
@@ -64,7 +66,7 @@ struct SceneView {
     int croot;                         // root as a leaf range (< 0) when the whole scene is one, else 0
     const float* __restrict__ grid;
     const float4* __restrict__ aux;
-    const double* __restrict__ A64;  // Sigma^-1 in binary64, 6 per primitive (a00 a01 a02 a11 a12 a22)
+    const double* __restrict__ A64;  // GF_A64 per primitive: a00 a01 a02 a11 a12 a22, r^2, pad
     int n;
     float r, r2;
     int G;

@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_tau(SceneView S, MaskView M, const floa
         if (M.prim_bits && !((M.prim_bits[P.orig >> 5] >> (P.orig & 31)) & 1u)) return;
         if (!active) return;
         HitGeom H;
-        if (!hit_geom(P, R, P.r2, S.A64 + (size_t)j * 6, H)) return;
+        if (!hit_geom(P, R, S.A64 + (size_t)j * GF_A64, H)) return;
         if (!lod_keep64(P, R, H, M.lod_k)) return;
         if (COUNT) ++nh;
         else acc += (double)hit_value(P, H, c_weid, c_weidL, c_weid64, c_weidL64);

@@ -1027,7 +1027,7 @@ static __device__ void bin_chord(const SceneView& S, const MaskView& M, const Se
     R.vx = st.sg.vx; R.vy = st.sg.vy; R.vz = st.sg.vz;
     R.tmin = lo; R.tmax = hi;
     HitGeom H;
-    if (!hit_geom(P, R, P.r2, S.A64 + (size_t)j * 6, H)) return;
+    if (!hit_geom(P, R, S.A64 + (size_t)j * GF_A64, H)) return;
     if (lod_drop(P, st.sg, (float)H.tc)) return;
     const double dlo = lo, dw = ((double)hi - dlo) / TK;
     const double ta = H.tc + H.uad * H.inv_n, tb = H.tc + H.ubd * H.inv_n;
@@ -1125,7 +1125,7 @@ static __device__ void exact_T_own(const SceneView& S, const MaskView& M, SegSta
         const float w = lm.w(P.cell);
         if (w == 0.0f || !prim_on(M, P.orig)) return;
         HitGeom H;
-        if (!hit_geom(P, R, P.r2, S.A64 + (size_t)j * 6, H)) return;
+        if (!hit_geom(P, R, S.A64 + (size_t)j * GF_A64, H)) return;
         if (lod_drop(P, sg, (float)H.tc)) return;
         acc += w * hit_value(P, H, c_weid_tr, c_weidL_tr, c_weid64_tr, c_weidL64_tr);
     });
