@@ -215,15 +215,19 @@ static __device__ float gl8_segment(float ua, float ub, double thc, double omc, 
 }
 
 // e^{-u^2/2} Re{e^{i psi(u)} w((sgn(u) Omega + i|u|)/sqrt 2)}: the part of
-// Re{e^{i theta} E(u)} that depends on the end point
+// Re{e^{i theta} E(u)} that depends on the end point; *mag receives
+// e^{-u^2/2} |w|, the size of the terms the real part is taken from (the
+// real part cancels when the phase lines up with w).
 static __device__ __forceinline__ float tail_term(float u, float Om, double thc, double omc,
-                                                  const float* __restrict__ wa, float wL) {
+                                                  const float* __restrict__ wa, float wL, float* mag) {
     const float is2 = 0.70710678118654752440f;
     float sg = u < 0.0f ? -1.0f : 1.0f;
     float2 w = wofz_weideman(sg * Om * is2, fabsf(u) * is2, wa, wL);
     float sp, cp;
     sincos2pi(frac_cycles(thc + (double)u * omc), &sp, &cp);
-    return __expf(-0.5f * u * u) * (cp * w.x - sp * w.y);
+    float e = __expf(-0.5f * u * u);
+    *mag = e * sqrtf(w.x * w.x + w.y * w.y);
+    return e * (cp * w.x - sp * w.y);
 }
 
 // The closed form entirely in binary64 (for hits whose float32 closed form
@@ -253,8 +257,10 @@ static __device__ float hit_value64(const PrimF& P, const HitGeom& H, const doub
 // tau_i (including rho alpha) of one hit with a non-empty chord.
 // Closed form: tau_i = pre Re{e^{i theta}[E(u_b) - E(u_a)]}, with
 // Re{e^{i theta}E(u)} = sgn(u) [exp(-Omega^2/2) cos theta - tail_term(u)].
-// Where that difference cancels (the segment integral is much smaller than
-// its terms, or the segment is short) float32 loses the digits:
+// Where that difference or a tail term's real part cancels (the segment
+// integral is much smaller than the terms it is made of, as for a strongly
+// oscillating kernel whose integral comes from its truncated ends, or the
+// segment is short) float32 loses the digits:
 // below 1e-4 whitened units the midpoint rule is used; short segments
 // (len (1 + |Omega| + max|u|) < 4) use 8-point Gauss-Legendre; where the
 // float32 closed form cancels by more than a factor 16 it is redone in
@@ -279,15 +285,17 @@ static __device__ __forceinline__ float hit_value(const PrimF& P, const HitGeom&
     float val, mag;
     if (H.enda && H.endb) {
         // unclipped chord: E(h) - E(-h) = 2 Re E(h)
-        float t = tail_term(H.half, Om, 0.0, H.omc, wa, wL);
+        float mt;
+        float t = tail_term(H.half, Om, 0.0, H.omc, wa, wL, &mt);
         float reE = eO - t;
         val = 2.0f * cth * reE;
-        mag = 2.0f * fabsf(cth) * (eO + fabsf(t));
+        mag = 2.0f * fabsf(cth) * (eO + mt);
     } else {
         float sa = H.ua < 0.0f ? -1.0f : 1.0f, sb = H.ub < 0.0f ? -1.0f : 1.0f;
-        float tb = tail_term(H.ub, Om, H.thc, H.omc, wa, wL), ta = tail_term(H.ua, Om, H.thc, H.omc, wa, wL);
+        float mb, ma;
+        float tb = tail_term(H.ub, Om, H.thc, H.omc, wa, wL, &mb), ta = tail_term(H.ua, Om, H.thc, H.omc, wa, wL, &ma);
         val = (sb - sa) * eO * cth - sb * tb + sa * ta;
-        mag = fabsf((sb - sa) * eO * cth) + fabsf(tb) + fabsf(ta);
+        mag = fabsf((sb - sa) * eO * cth) + mb + ma;
     }
     if (mag > 16.0f * fabsf(val)) return hit_value64(P, H, wa64, wL64);
     return pre * val;
