@@ -297,6 +297,20 @@ gf_status gf_render_workspace_size(gf_scene scene, const gf_camera* cam, const g
 gf_status gf_render(gf_scene scene, const gf_camera* cam, const gf_render_desc* desc, void* workspace,
                     size_t ws_bytes, float* radiance, float* primary_T, void* stream);
 
+/* gf_render without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * file-scope device array of the library: the rays of up to 1,048,576
+ * pixels and the tracking state of 1024 resident waves, about 100 MB that
+ * each device the library runs on holds until the process ends.  A camera
+ * with more pixels returns GF_EINVAL before any launch.  Outputs as
+ * gf_render (radiance device height x width; primary_T device height x
+ * width or NULL), bitwise the same.  Every call on one device shares the
+ * array, which keeps the last call's contents: calls that overlap on one
+ * device (other streams, other threads) race. */
+gf_status gf_render_noalloc(gf_scene scene, const gf_camera* cam, const gf_render_desc* desc, float* radiance,
+                            float* primary_T, void* stream);
+
 /* Adjoint of gf_optical_depth (and of T = exp(-tau)): the gradient of a
  * rendered optical-depth / transmittance image with respect to every
  * primitive parameter, which the regression of Sec. 5 (differentiable

@@ -79,6 +79,7 @@ _SIGS = {
     "gf_render_rays": [_vp, _vp, _i64, _i, C.POINTER(gf_render_desc), _vp, _vp, _vp, _vp, _vp],
     "gf_render_workspace_size": [_vp, C.POINTER(gf_camera), C.POINTER(gf_render_desc), C.POINTER(C.c_size_t)],
     "gf_render": [_vp, C.POINTER(gf_camera), C.POINTER(gf_render_desc), _vp, C.c_size_t, _vp, _vp, _vp],
+    "gf_render_noalloc": [_vp, C.POINTER(gf_camera), C.POINTER(gf_render_desc), _vp, _vp, _vp],
     "gf_render_counts": [_vp, _vp, _i64, _i, C.POINTER(gf_render_desc), _vp, _vp],
     "gf_camera_rays": [C.POINTER(gf_camera), _vp, _vp],
     "gf_optical_depth_backward": [_vp, _vp, _i64, _i, gf_mask, _vp, _vp, _vp, _vp, _vp],
@@ -294,6 +295,16 @@ def gf_render(scene: Scene, cam, desc: gf_render_desc, workspace: torch.Tensor, 
 
 
 GF_RENDER_COUNTS = 7
+
+
+def gf_render_noalloc(scene: Scene, cam, desc: gf_render_desc, want_T=True):
+    """gf_render with the library's own fixed workspace (no allocation in
+    the call; the output tensors are allocated here, by the caller)."""
+    rad = torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda")
+    T = torch.empty_like(rad) if want_T else None
+    _check(lib().gf_render_noalloc(scene.handle, C.byref(cam), C.byref(desc), _ptr(rad), _ptr(T, optional=True),
+                                   _stream()))
+    return rad, T
 
 
 def gf_render_counts(scene: Scene, rays, desc: gf_render_desc, image_width=0):
