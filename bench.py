@@ -5,10 +5,11 @@ Workload (default): 100k Gabor primitives from the 64-blob field, a 512x512
 pinhole camera, LOD masks {full, 1/2 band, 1/4 band, 45-degree cone about +z}.
 One step runs the whole path on that batch:
   scene build (validation, Morton keys, radix sort, Karras tree, refit,
-  traversal records, majorant grid) + cone mask, then for every mask
+  traversal records) + cone mask, then for every mask
   deterministic optical depth / transmittance of the 512^2 rays and an 8-spp
-  single-scattering render (weighted delta tracking, ratio-tracked shadow rays,
-  isotropic phase, albedo 0.9).
+  single-scattering render (weighted delta tracking of the camera segment,
+  shadow transmittance in closed form -- or ratio-tracked with
+  --ratio-shadow --, isotropic phase, albedo 0.9).
 value = (transmittance rays + render camera samples) / s over the step.
 
 After the timed steps (not part of them) the run measures the serving trace
@@ -58,10 +59,13 @@ def parse():
                     help="leave the single-scattering render out of the step (optical depth only)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=8)
+    ap.add_argument("--serving-requests", type=int, default=12)
+    ap.add_argument("--serving-sweep", action="store_true", help="serving at 0.35, 0.7, 1.0, 1.4 x saturation")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--bin", default="mixture", help="orientation-bin strategy of the multiple-scattering workload")
+    ap.add_argument("--ratio-shadow", action="store_true",
+                    help="ratio-tracked shadow transmittance (default: closed form exp(-tau))")
     return ap.parse_args()
 
 
@@ -102,7 +106,8 @@ def main():
                 gf.make_mask(gf.FULL_CELLS, bits)], bits
 
     def desc(mask):
-        return gf.render_desc(spp=args.spp, multiple=False, albedo=0.9, env=1.0, mask=mask, seed=1234)
+        return gf.render_desc(spp=args.spp, multiple=False, albedo=0.9, env=1.0, mask=mask, seed=1234,
+                              exact_shadow=not args.ratio_shadow)
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     timings = {"build": [], "tau": [[] for _ in range(4)], "render": [[] for _ in range(4)]}
@@ -197,7 +202,9 @@ def main():
         "dtype": "f32 (f64 geometry setup)", "data": "synthetic",
         "config": {"workload": "%s: %s, %dx%d pinhole, masks %s%s"
                    % (name, W.describe(name), width, width, "/".join(mask_names),
-                      ", %d-spp single scattering" % args.spp if args.render else ", optical depth and transmittance"),
+                      (", %d-spp single scattering (delta-tracked free flights, %s shadow transmittance)"
+                       % (args.spp, "ratio-tracked" if args.ratio_shadow else "closed-form"))
+                      if args.render else ", optical depth and transmittance"),
                    "global_batch": npix, "parallelism": "single GPU"},
         "roofline": roofline,
         "per_mask": {mask_names[k]: {"tau_ms": round(tau_ms[k], 3), "tau_Mrays_s": round(npix / tau_ms[k] / 1e3, 1),
@@ -397,32 +404,42 @@ def multiple_scattering_cpu(args, np, params, rays, rho, Tm, Tv, spp, units, ms_
 
 
 def serving(args, gf, W, np, torch):
-    """Poisson trace over four resident scenes, continuous batching vs FIFO plain."""
+    """Poisson trace over four resident scenes, continuous batching vs the
+    plain per-request renderer (FIFO, one request at a time, caller
+    workspace).  The request rate is a multiple of the plain renderer's
+    saturation rate on this trace (0.7 by default; --serving-sweep runs
+    several), and the server's memory budget (64 MB of camera rays, two
+    1024^2 requests) makes admission bind."""
     import gen
     from paper_2602_05081_amd import serve
     scenes = [gf.Scene(torch.as_tensor(W.scene(s)).cuda(), rho=W.rho(s)) for s in W.SERVE_SCENES]
     n = args.serving_requests
     reqs = gen.serving_requests(n, seed=5)
+    budget = 64 << 20
     # warm both paths
     serve.run_plain(scenes, reqs[:1], np.zeros(1))
     # saturation throughput of the plain renderer on this trace decides the rate
     t0 = time.perf_counter()
-    serve.run_plain(scenes, reqs[:3], np.zeros(3))
-    plain_rate = 3 / (time.perf_counter() - t0)
-    qps = 0.7 * plain_rate
-    arrivals = gen.poisson_arrivals(n, qps, seed=6)
-    log("serving: plain renderer saturates at %.3f requests/s; replaying %d requests at %.3f/s" % (plain_rate, n, qps))
+    k = min(4, n)
+    serve.run_plain(scenes, reqs[:k], np.zeros(k))
+    plain_rate = k / (time.perf_counter() - t0)
+    out = {"requests": n, "scenes": W.SERVE_SCENES, "mem_budget": budget,
+           "plain_saturation_qps": round(plain_rate, 4), "points": []}
+
     def done(tag):
         return lambda k, t: log("serving (%s): request %d done at %.1f s" % (tag, k, t))
 
-    lat_s, mk_s, _, held = serve.run_server(scenes, reqs, arrivals, mem_budget=1 << 30, tile_rays=4096,
-                                            max_tiles=192, time_limit=600, on_done=done("batching"))
-    log("serving: continuous batching done in %.1f s" % mk_s)
-    lat_p, mk_p, _ = serve.run_plain(scenes, reqs, arrivals, time_limit=600, on_done=done("plain"))
-    log("serving: plain renderer done in %.1f s" % mk_p)
-    out = {"qps": round(qps, 2), "requests": n, "scenes": W.SERVE_SCENES,
-           "continuous_batching": serve.summarize(lat_s, mk_s, reqs),
-           "plain_per_request": serve.summarize(lat_p, mk_p, reqs), "max_bytes_held": held}
+    for f in ([0.35, 0.7, 1.0, 1.4] if args.serving_sweep else [0.7]):
+        qps = f * plain_rate
+        arrivals = gen.poisson_arrivals(n, qps, seed=6)
+        log("serving: %.2f x saturation = %.3f requests/s, %d requests" % (f, qps, n))
+        lat_s, mk_s, _, held = serve.run_server(scenes, reqs, arrivals, mem_budget=budget, tile_rays=4096,
+                                                max_tiles=192, time_limit=1800, on_done=done("batching"))
+        lat_p, mk_p, _ = serve.run_plain(scenes, reqs, arrivals, time_limit=1800, on_done=done("plain"))
+        out["points"].append({"load": f, "qps": round(qps, 4),
+                              "continuous_batching": serve.summarize(lat_s, mk_s, reqs),
+                              "plain_per_request": serve.summarize(lat_p, mk_p, reqs),
+                              "max_bytes_held": held})
     for s in scenes:
         s.close()
     return out

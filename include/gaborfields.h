@@ -342,8 +342,10 @@ typedef struct {
 /* mem_budget: bytes of device workspace the admitted requests may hold at
  * once (each request holds width*height*32 bytes of rays while in flight).
  * tile_rays: rays per tile; max_tiles: tiles per device batch.  The server
- * also allocates, once, the tracking workspace of one batch (at most
- * 3072 x 62 KB).  GF_ENOMEM / GF_EDEVICE if an allocation fails. */
+ * also allocates, once, two batch slots, each with its own stream (default
+ * priority) and tracking workspace (at most 3072 x 64 KB), so that a batch
+ * starts while the previous one drains.  Ray generation runs on `stream`.
+ * GF_ENOMEM / GF_EDEVICE if an allocation fails. */
 gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_tiles, void* stream, gf_server* out);
 gf_status gf_server_destroy(gf_server server);
 /* Queues a request (non-blocking); *id receives its id.  GF_EINVAL if it can
@@ -352,8 +354,10 @@ gf_status gf_server_submit(gf_server server, const gf_request* req, uint64_t* id
 /* Advances the scheduler: admits queued requests (FIFO) while memory allows,
  * launches the next batch of tiles from the admitted requests, shortest
  * remaining work first (rays left x samples, multiple scattering counted 3x),
- * and retires requests whose tiles have all completed.  At most two batches
- * are in flight.  Non-blocking unless `wait` != 0. */
+ * on a free batch slot, and retires requests whose tiles have all completed.
+ * At most two batches are in flight, on the two slot streams, overlapping.
+ * The server renders delta-tracked requests (free_flight 0).  Non-blocking
+ * unless `wait` != 0. */
 gf_status gf_server_step(gf_server server, int wait);
 /* Retrieves up to max finished request ids (in completion order). */
 gf_status gf_server_poll(gf_server server, uint64_t* ids, int max, int* n_done);

@@ -46,7 +46,7 @@ static __device__ __forceinline__ Cf csub(Cf a, Cf b) { return {a.r - b.r, a.i -
 static __device__ __forceinline__ Cf cscale(Cf a, float s) { return {a.r * s, a.i * s}; }
 static __device__ __forceinline__ Cf cexpi_cycles(double c) {
     float s, co;
-    sincos2pi(frac_cycles(c), &s, &co);
+    sincos_cycles(c, &s, &co);
     return {co, s};
 }
 

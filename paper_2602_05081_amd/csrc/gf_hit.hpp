@@ -205,8 +205,8 @@ static __device__ float gl8_segment(float ua, float ub, double thc, double omc, 
             float d = h * c_gl8x[k];
             float u1 = c - d, u2 = c + d;
             float s1, c1, s2, c2;
-            sincos2pi(frac_cycles(thc + (double)u1 * omc), &s1, &c1);
-            sincos2pi(frac_cycles(thc + (double)u2 * omc), &s2, &c2);
+            sincos_cycles(thc + (double)u1 * omc, &s1, &c1);
+            sincos_cycles(thc + (double)u2 * omc, &s2, &c2);
             part += c_gl8w[k] * (__expf(-0.5f * u1 * u1) * c1 + __expf(-0.5f * u2 * u2) * c2);
         }
         acc += part * h;
@@ -224,7 +224,7 @@ static __device__ __forceinline__ float tail_term(float u, float Om, double thc,
     float sg = u < 0.0f ? -1.0f : 1.0f;
     float2 w = wofz_weideman(sg * Om * is2, fabsf(u) * is2, wa, wL);
     float sp, cp;
-    sincos2pi(frac_cycles(thc + (double)u * omc), &sp, &cp);
+    sincos_cycles(thc + (double)u * omc, &sp, &cp);
     float e = __expf(-0.5f * u * u);
     *mag = e * sqrtf(w.x * w.x + w.y * w.y);
     return e * (cp * w.x - sp * w.y);
@@ -274,13 +274,13 @@ static __device__ __forceinline__ float hit_value(const PrimF& P, const HitGeom&
     if (len < 1e-4f) {
         float um = 0.5f * (H.ua + H.ub);
         float sp, cp;
-        sincos2pi(frac_cycles(H.thc + (double)um * H.omc), &sp, &cp);
+        sincos_cycles(H.thc + (double)um * H.omc, &sp, &cp);
         return pre * sq2pi * len * __expf(-0.5f * um * um) * cp;
     }
     float q = len * (1.0f + fabsf(Om) + fmaxf(fabsf(H.ua), fabsf(H.ub)));
     if (q < 4.0f) return pre * sq2pi * gl8_segment(H.ua, H.ub, H.thc, H.omc, 1);
     float sth, cth;
-    sincos2pi(frac_cycles(H.thc), &sth, &cth);
+    sincos_cycles(H.thc, &sth, &cth);
     float eO = __expf(-0.5f * Om * Om);
     float val, mag;
     if (H.enda && H.endb) {

@@ -172,11 +172,27 @@ static __device__ __forceinline__ uint64_t lanemask_lt() {
 
 static __device__ __forceinline__ int uniform_int(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// fractional part in [-0.5, 0.5] of a phase given in cycles (binary64)
-static __device__ __forceinline__ float frac_cycles(double c) { return (float)(c - rint(c)); }
 
 // sin / cos of 2 pi x for |x| <= 0.5
 static __device__ __forceinline__ void sincos2pi(float x, float* s, float* c) { sincospif(2.0f * x, s, c); }
+
+// sin and cos of 2 pi c for a phase c in cycles (binary64), each with a
+// small relative error also near its zeros: c is reduced to the nearest
+// quarter cycle q / 4 in binary64, the remainder x (|x| <= 1/8) becomes
+// float32 with full relative precision, and q mod 4 turns sin / cos of
+// 2 pi x into those of 2 pi c.
+static __device__ __forceinline__ void sincos_cycles(double c, float* s, float* co) {
+    const double q = rint(4.0 * c);
+    const float x = (float)(c - 0.25 * q);
+    float sx, cx;
+    sincospif(2.0f * x, &sx, &cx);
+    switch ((int)((long long)q & 3)) {
+        case 0: *s = sx; *co = cx; break;
+        case 1: *s = cx; *co = -sx; break;
+        case 2: *s = -sx; *co = -cx; break;
+        default: *s = -cx; *co = sx; break;
+    }
+}
 
 // Philox4x32-10 (Salmon et al., SC 2011): 10 rounds of two 32x32->64
 // multiplications with Weyl-sequence key bumps.

@@ -4,15 +4,18 @@
 // Memory: the server owns one device pool of `mem_budget` bytes, carved by a
 // first-fit allocator; an admitted request holds width*height*32 bytes of
 // camera rays there until its last tile completes.  No device allocation
-// happens while serving; the tracking workspace of one batch is allocated
-// with the server.
+// happens while serving; the tracking workspaces of the two batch slots are
+// allocated with the server.
 // Scheduling: requests wait in FIFO order until their rays fit the pool; an
-// admitted request's rays are generated on the device right away.  Each step
-// assembles one batch of up to `max_tiles` tiles of `tile_rays` rays from the
-// admitted requests, shortest remaining work first (rays left x samples,
-// multiple scattering weighted 3x), and launches it as a single kernel; up to
-// two batches are in flight, each followed by an event.  A request finishes
-// when the events of all its tiles have completed.
+// admitted request's rays are generated on the device right away (on the
+// caller's stream).  Each step assembles one batch of up to `max_tiles`
+// tiles of `tile_rays` rays from the admitted requests, shortest remaining
+// work first (rays left x samples, multiple scattering weighted 3x), and
+// launches it as a single kernel.  Two batch slots, each with its own
+// stream (default priority), workspace and event, let a batch start while
+// the previous one drains its last chunks; each slot stream first waits for
+// the ray generation queued before its launch.  A request finishes when the
+// events of all its tiles have completed.
 // The API is single-threaded: all calls on one server come from one thread.
 #include <string.h>
 
@@ -50,9 +53,11 @@ struct Batch {
 struct gf_server_s {
     gfs::Pool mem;  // offsets into `pool`
     int tile_rays, max_tiles;
-    hipStream_t stream;
+    hipStream_t stream;  // the caller's: ray generation
     char* pool;
-    float* ws;  // tracking workspace of one batch (batches run in stream order)
+    float* ws[kSlots];           // tracking workspace of each batch slot
+    hipStream_t sstream[kSlots];  // each slot's stream
+    hipEvent_t rays_ready;        // ray generation done (waited on by the slots)
     std::deque<Req*> queue;
     std::vector<Req*> active;
     std::map<uint64_t, Req*> byid;
@@ -80,11 +85,13 @@ extern "C" gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_
     S->stream = (hipStream_t)stream;
     S->next_id = 1;
     S->pool = nullptr;
-    S->ws = nullptr;
+    S->rays_ready = nullptr;
     for (int k = 0; k < kSlots; ++k) {
         S->slot_busy[k] = false;
         S->hreq[k] = S->htile[k] = S->dreq[k] = S->dtile[k] = nullptr;
         S->events[k] = nullptr;
+        S->ws[k] = nullptr;
+        S->sstream[k] = nullptr;
     }
     auto fail = [&](hipError_t e, const char* what) {
         gf_server_destroy(S);
@@ -92,9 +99,13 @@ extern "C" gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_
     };
     hipError_t e = hipMalloc((void**)&S->pool, S->mem.budget);
     if (e != hipSuccess) return fail(e, "hipMalloc(pool)");
-    e = hipMalloc((void**)&S->ws, gf_serve_workspace_bytes(max_tiles, tile_rays));
-    if (e != hipSuccess) return fail(e, "hipMalloc(workspace)");
+    if ((e = hipEventCreateWithFlags(&S->rays_ready, hipEventDisableTiming)) != hipSuccess)
+        return fail(e, "hipEventCreate");
     for (int k = 0; k < kSlots; ++k) {
+        if ((e = hipMalloc((void**)&S->ws[k], gf_serve_workspace_bytes(max_tiles, tile_rays))) != hipSuccess)
+            return fail(e, "hipMalloc(workspace)");
+        if ((e = hipStreamCreateWithFlags(&S->sstream[k], hipStreamNonBlocking)) != hipSuccess)
+            return fail(e, "hipStreamCreate");
         if ((e = hipHostMalloc((void**)&S->hreq[k], gf_serve_req_size() * max_tiles)) != hipSuccess)
             return fail(e, "hipHostMalloc");
         if ((e = hipHostMalloc((void**)&S->htile[k], gf_serve_tile_size() * max_tiles)) != hipSuccess)
@@ -114,6 +125,11 @@ extern "C" gf_status gf_server_destroy(gf_server S) {
     if (!S) return gf_fail(GF_EINVAL, "gf_server_destroy: NULL server");
     if (S->stream || S->pool) (void)hipStreamSynchronize(S->stream);
     for (int k = 0; k < kSlots; ++k) {
+        if (S->sstream[k]) {
+            (void)hipStreamSynchronize(S->sstream[k]);
+            (void)hipStreamDestroy(S->sstream[k]);
+        }
+        if (S->ws[k]) (void)hipFree(S->ws[k]);
         if (S->hreq[k]) (void)hipHostFree(S->hreq[k]);
         if (S->htile[k]) (void)hipHostFree(S->htile[k]);
         if (S->dreq[k]) (void)hipFree(S->dreq[k]);
@@ -121,7 +137,7 @@ extern "C" gf_status gf_server_destroy(gf_server S) {
         if (S->events[k]) (void)hipEventDestroy(S->events[k]);
     }
     if (S->pool) (void)hipFree(S->pool);
-    if (S->ws) (void)hipFree(S->ws);
+    if (S->rays_ready) (void)hipEventDestroy(S->rays_ready);
     for (auto& kv : S->byid) delete kv.second;
     delete S;
     return GF_OK;
@@ -226,11 +242,14 @@ static gf_status launch_batch(gf_server_s* S) {
         ++ntiles;
     }
     for (auto& kv : rays_in) b.work.push_back(kv);
-    GF_HIP(hipMemcpyAsync(S->dreq[slot], hreq, gf_serve_req_size() * nreq, hipMemcpyHostToDevice, S->stream));
-    GF_HIP(hipMemcpyAsync(S->dtile[slot], htile, gf_serve_tile_size() * ntiles, hipMemcpyHostToDevice, S->stream));
-    gf_status st = gf_serve_launch(S->dreq[slot], S->dtile[slot], ntiles, S->tile_rays, S->ws, S->stream);
+    hipStream_t sm = S->sstream[slot];
+    GF_HIP(hipEventRecord(S->rays_ready, S->stream));
+    GF_HIP(hipStreamWaitEvent(sm, S->rays_ready, 0));
+    GF_HIP(hipMemcpyAsync(S->dreq[slot], hreq, gf_serve_req_size() * nreq, hipMemcpyHostToDevice, sm));
+    GF_HIP(hipMemcpyAsync(S->dtile[slot], htile, gf_serve_tile_size() * ntiles, hipMemcpyHostToDevice, sm));
+    gf_status st = gf_serve_launch(S->dreq[slot], S->dtile[slot], ntiles, S->tile_rays, S->ws[slot], sm);
     if (st != GF_OK) return st;
-    GF_HIP(hipEventRecord(b.ev, S->stream));
+    GF_HIP(hipEventRecord(b.ev, sm));
     S->slot_busy[slot] = true;
     S->inflight.push_back(b);
     return GF_OK;

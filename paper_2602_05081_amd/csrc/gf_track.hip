@@ -1324,11 +1324,12 @@ static __device__ void render_rays(const SceneView& S, const MaskView& M, const 
         while (__any(more)) {
             if (more) {
                 bool fin;
-                if (EXACT) {
-                    exact_segment<COUNT, false>(S, M, rl.st, true, lm, pstk, wk);
-                    fin = true;
-                } else if (FF == 1 && rl.shadow) {
+                if (rl.shadow && FF >= 1) {
+                    // transmittance only: one closed-form pass, no bins
                     exact_T_own<COUNT>(S, M, rl.st, lm, wk);
+                    fin = true;
+                } else if (EXACT) {
+                    exact_segment<COUNT, false>(S, M, rl.st, true, lm, pstk, wk);
                     fin = true;
                 } else {
                     fin = track_own<COUNT>(S, M, rl.st, lm, wk);

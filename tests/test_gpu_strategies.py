@@ -106,19 +106,21 @@ def test_stochastic_radiance_matches_oracle(level, bin, multiple):
 
 
 def _blob100k_masks(gf, scene, params):
-    lod = [gf.gf_mask_lod_cells(k) for k in (1, 2)]
+    lod = [gf.gf_mask_lod_cells(k) for k in (1, 2, 3)]
     gbits = gf.gf_mask_cone(scene)
     obits = oracle.mask_cone(params)
     return [("half_band", gf.make_mask(lod[0]), dict(cells=lod[0])),
             ("quarter_band", gf.make_mask(lod[1]), dict(cells=lod[1])),
+            ("eighth_band", gf.make_mask(lod[2]), dict(cells=lod[2])),
             ("cone45", gf.make_mask(gf.FULL_CELLS, gbits), dict(bits=obits))]
 
 
 def test_masked_renders_blob100k_sampled():
     """The benchmark's render (100k Gabors, 512^2 pinhole camera, 8-spp
-    single scattering) under the 1/2 band, 1/4 band and 45-degree cone
-    masks: 24 sampled pixels, each ray repeated so that its copies pool many
-    samples, against the oracle's render of the same pixels."""
+    single scattering) under the 1/2, 1/4 and 1/8 band (the serving
+    workload's levels) and 45-degree cone masks: 24 sampled pixels, each
+    ray repeated so that its copies pool many samples, against the oracle's
+    render of the same pixels."""
     gf = require_gpu()
     params, rays, rho = W.scene("blob100k"), W.rays("blob100k"), W.rho("blob100k")
     scene = gf.Scene(dev(params), rho=rho)
