@@ -84,6 +84,8 @@ def main():
     torch.cuda.init()
     if args.workload.startswith("blob1m"):
         return multiple_scattering_bench(args)
+    if args.ratio_shadow:
+        KERNELS["render"] = "void k_render<false, 0>"
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -160,17 +162,22 @@ def main():
     units = 4 * npix * (1 + spp_r)
     value = units / (ms_per_step * 1e-3) / 1e6
 
-    # algorithmic work of the timed launches (same inputs and seeds)
+    # algorithmic work of the timed launches: optical depth counted exactly on
+    # the same launch; the render's work per sample counted on every 16th
+    # pixel row (the counting variant walks a point query per consumed
+    # tentative point, which takes ~25x the render) and scaled to the frame
     scene = gf.Scene(params, rho)
     masks, bits = masks_for(scene)
     tau_bytes, ren_bytes, ren_counts = [], [], []
+    stride = 16
+    sub_rays = rays.view(width, width, 8)[::stride].reshape(-1, 8).contiguous()
     for k, m in enumerate(masks):
         log("counting work of mask %s" % mask_names[k])
         nodes, hits = gf.gf_optical_depth_counts(scene, rays, m, image_width=width)
         nn, nh = int(nodes.sum().item()), int(hits.sum().item())
         tau_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + PRIM_BYTES * nh + NODE_BYTES * nn)
         if args.render:
-            c = gf.gf_render_counts(scene, rays, desc(m), image_width=width)
+            c = [v * stride for v in gf.gf_render_counts(scene, sub_rays, desc(m), image_width=0)]
             ren_counts.append(c)
             ren_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + NODE_BYTES * c[5] + PRIM_BYTES * c[6])
         else:
@@ -190,6 +197,11 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": prof.get("traffic"), "kernel": KERNELS[dominant],
                 "algorithmic_bytes_per_launch": int(alg), "launch_ms": round(1e3 * per_launch_s, 3)}
+    if dominant == "render" and ren_counts:
+        # the same rate with the kernel's own reads (32 B per internal node it
+        # visits, 60 B per primitive record it reads) in place of point queries
+        kr = sum(npix * (RAY_BYTES + OUT_BYTES) + NODE_BYTES * c[1] + PRIM_BYTES * c[2] for c in ren_counts) / 4
+        roofline["frac_kernel_reads"] = round(kr / per_launch_s / 1e9 / PEAK_HBM_GBS, 4)
     if prof.get("traffic"):
         roofline["measured_frac"] = round(prof["traffic"] / per_launch_s / 1e9 / PEAK_HBM_GBS, 4)
     if prof.get("valu_insts"):
@@ -227,7 +239,7 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-KERNELS = {"render": "void k_render<false, false>", "optical_depth": "void k_tau<false>"}
+KERNELS = {"render": "void k_render<false, 1>", "optical_depth": "void k_tau<false>"}
 
 
 def work_per_sample(counts, k, samples):

@@ -232,7 +232,11 @@ typedef struct {
                            transmittances exp(-tau) from the closed form */
     int transmittance;  /* free_flight 0, single scattering: the shadow segment's transmittance by
                            0 ratio tracking, 1 the closed form exp(-tau) (Sec. 4.4; the tomography case
-                           of Sec. 4.6); same mean, no variance.  free_flight 1 always uses 1. */
+                           of Sec. 4.6); same mean, no variance.  free_flight 1 always uses 1.
+                           With 1 in an image launch (image_width > 0) the shadow direction of a
+                           sample is shared by the rays of an 8x8 pixel tile (drawn from the
+                           tile's stream): each ray's estimate stays unbiased and the tile's
+                           shadow rays trace as one packet; a ray list draws one per ray. */
     uint64_t shadow_cells; /* single scattering: cells the shadow rays trace, fixed (Zero-NEE of
                               Sec. 4.6 implementation details: shadow rays against the low-pass level,
                               cells 0x7); 0 = the shadow segment's own mask */

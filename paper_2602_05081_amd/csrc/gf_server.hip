@@ -149,8 +149,9 @@ extern "C" gf_status gf_server_submit(gf_server S, const gf_request* q, uint64_t
     gf_status st = gf_check_camera(&q->camera, "gf_server_submit");
     if (st == GF_OK) st = gf_check_render_desc(&q->render, "gf_server_submit");
     if (st != GF_OK) return st;
-    if (q->render.free_flight != 0)
-        return gf_fail(GF_EINVAL, "gf_server_submit: the server batches delta-tracked renders only (free_flight 0)");
+    if (q->render.free_flight != 0 || q->render.transmittance != 0)
+        return gf_fail(GF_EINVAL, "gf_server_submit: the server batches delta-tracked renders with ratio-tracked "
+                                  "transmittance only (free_flight 0, transmittance 0)");
     if (q->scene->depth > 64) return gf_fail(GF_EINVAL, "gf_server_submit: scene LBVH deeper than 64");
     size_t bytes = gfs::request_bytes(q->camera.width, q->camera.height);
     if (bytes > S->mem.budget)

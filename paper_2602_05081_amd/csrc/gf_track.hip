@@ -970,6 +970,7 @@ struct RenderArgs {
     float albedo, hg, env;
     Strat strat;
     uint32_t shadow_cells;  // 0: shadow segments draw their own mask
+    int tile_w;             // image width of the launch's 8x8 tiles (0: a ray list)
     uint64_t seed;
 };
 
@@ -1133,6 +1134,34 @@ static __device__ void exact_T_own(const SceneView& S, const MaskView& M, SegSta
     st.live = false;
 }
 
+// Exact transmittance of the segments of a whole wave in one packet walk
+// (the rays of a tile's shadow segments share their direction, so the
+// packet stays coherent); every lane of the wave calls it.
+template <bool COUNT>
+static __device__ void exact_T_packet(const SceneView& S, const MaskView& M, SegState& st, bool act, const LaneMem& lm,
+                                      int* pstk, Work& wk) {
+    act = act && st.live;
+    RayD R;
+    R.ox = st.sg.ox; R.oy = st.sg.oy; R.oz = st.sg.oz;
+    R.vx = st.sg.vx; R.vy = st.sg.vy; R.vz = st.sg.vz;
+    R.tmin = st.sg.ta; R.tmax = st.sg.tb;
+    float acc = 0.0f;
+    packet_walk<COUNT>(S, st, act, st.sg.ta, st.sg.tb, pstk, wk, [&](int j) {
+        PrimF P = load_prim(S.prims, j);
+        if (COUNT) ++wk.prims;
+        const float w = lm.w(P.cell);
+        if (w == 0.0f || !prim_on(M, P.orig)) return;
+        HitGeom H;
+        if (!hit_geom(P, R, S.A64 + (size_t)j * GF_A64, H)) return;
+        if (lod_drop(P, st.sg, (float)H.tc)) return;
+        acc += w * hit_value(P, H, c_weid_tr, c_weidL_tr, c_weid64_tr, c_weidL64_tr);
+    });
+    if (act) {
+        st.T = __expf(-acc);
+        st.live = false;
+    }
+}
+
 // Camera segments of a whole wave, window by window: packet proposal and
 // packet evaluation passes; a lane whose segment is finished sits out.
 template <bool COUNT>
@@ -1230,6 +1259,37 @@ struct RenderLane {
         s2 += L * L;
         return true;
     }
+    // Single scattering with a closed-form shadow transmittance in an image
+    // launch: the rest of sample s from its camera outcome, with the
+    // shadow direction drawn from the stream of the ray's 8x8 pixel tile
+    // (seed, tile, sample, 3), shared by the tile's rays.  Each ray's
+    // direction is still uniform on the sphere and independent of its
+    // camera segment, so its estimate is unbiased; the tile's shadow rays
+    // are parallel and trace as one packet.  Returns true when a shadow
+    // segment was set up (false: the sample is over).
+    __device__ bool begin_shadow(const SceneView& S, const MaskView& M, const RenderArgs& A, int s, float tc,
+                                 float wf, uint32_t tile) {
+        g.init(A.seed, key, (uint32_t)s, 2u);
+        L = 0.0f;
+        nsc = seg = 0;
+        w = wf;
+        if (!(tc < INFINITY)) {
+            L += w * A.env;
+            shadow = false;
+            end_sample();
+            return false;
+        }
+        float x[3] = {r[0] + tc * r[3], r[1] + tc * r[4], r[2] + tc * r[5]};
+        Rng gt;
+        gt.init(A.seed, tile, (uint32_t)s, 3u);
+        float d[3];
+        sample_sphere(gt, d);
+        shadow = true;
+        seg = 1;
+        CellW cw = A.shadow_cells ? fixed_weights(A.shadow_cells & M.cells, wl) : weights(S, M, A, d);
+        begin_segment(S, st, x, d, 0.0f, INFINITY, cw, MODE_RATIO, 0.0f, g);
+        return true;
+    }
     // the current segment is finished: scatter (and set up the next
     // segment) or close the sample; true when the sample is over
     __device__ bool segment_done(const SceneView& S, const MaskView& M, const RenderArgs& A) {
@@ -1309,6 +1369,16 @@ static __device__ void render_rays(const SceneView& S, const MaskView& M, const 
                 lm.ctc(k) = rl.st.tc;
                 lm.cwf(k) = rl.st.wf;
             }
+        }
+        if (FF == 1 && !A.multiple && A.tile_w > 0) {
+            // shadow segments of the group's samples as packets
+            const uint32_t tile = valid ? (uint32_t)((idx / A.tile_w >> 3) * (A.tile_w >> 3) + (idx % A.tile_w >> 3)) : 0u;
+            for (int k = 0; k < gn; ++k) {
+                const bool sh = valid && rl.begin_shadow(S, M, A, s0 + k, lm.ctc(k), lm.cwf(k), tile);
+                exact_T_packet<COUNT>(S, M, rl.st, sh, lm, pstk, wk);
+                if (sh) rl.segment_done(S, M, A);
+            }
+            continue;
         }
         int k = 0;
         // the next sample of the group whose path goes on past the camera
@@ -1514,6 +1584,7 @@ static RenderArgs render_args(const gf_render_desc* d) {
     A.strat.beta = d->beta;
     A.strat.delta = d->delta;
     A.shadow_cells = (uint32_t)(d->shadow_cells & 0xFFFu);
+    A.tile_w = 0;
     A.seed = d->seed;
     return A;
 }
@@ -1653,7 +1724,8 @@ extern "C" gf_status gf_transmittance_ratio(gf_scene s, const float* rays, int64
 static gf_status render_launch(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
                                float* ws, float* L_mean, float* L_var, float* T_mean, float* T_var, hipStream_t sm,
                                unsigned long long* counters, unsigned max_waves = TR_RES_BLOCKS) {
-    const RenderArgs A = render_args(d);
+    RenderArgs A = render_args(d);
+    A.tile_w = image_width;
     const int ff = A.exact ? 2 : (d->transmittance ? 1 : 0);
     if (ff) {
         gf_status st = gf_ensure_weideman_track();

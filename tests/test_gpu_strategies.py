@@ -351,3 +351,23 @@ def test_closed_form_shadow_transmittance():
     o, ov, _, _ = oracle.render(params, rs, 256, seed=4, rho=rho, multiple=False, albedo=0.9)
     pooled, worst = _pooled(g, o, np.sqrt(gv + ov / 256))
     assert pooled < 3.0 and worst < 6.0, (pooled, worst)
+
+
+def test_tile_shared_shadow_directions_image_launch():
+    """Single scattering with closed-form shadow transmittance in an image
+    launch (8x8 tiles sharing each sample's shadow direction, packet shadow
+    walks): one pixel per tile against the oracle's render in mean, and the
+    launch differs from a ray-list launch of the same rays (which draws one
+    direction per ray)."""
+    gf = require_gpu()
+    params, rays, rho = W.scene("tiny256"), W.rays("tiny256"), W.rho("tiny256")
+    scene = gf.Scene(dev(params), rho=rho)
+    spp = 2048
+    d = gf.render_desc(spp=spp, multiple=False, albedo=0.9, seed=15, exact_shadow=True)
+    L, Lv, _, _ = (host(x) for x in gf.gf_render_rays(scene, dev(rays), d, image_width=64))
+    px = np.array([(8 * ty + 3) * 64 + 8 * tx + 5 for ty in range(8) for tx in range(8)])
+    o, ov, _, _ = oracle.render(params, rays[px], 1024, seed=9, rho=rho, multiple=False, albedo=0.9)
+    pooled, worst = _pooled(L[px], o, np.sqrt(Lv[px] / spp + ov / 1024))
+    assert pooled < 3.0 and worst < 5.0, (pooled, worst)
+    Ll, _, _, _ = (host(x) for x in gf.gf_render_rays(scene, dev(rays), d, image_width=0))
+    assert not np.array_equal(L, Ll)

@@ -172,17 +172,22 @@ def test_render_deterministic_and_batch_independent():
 
 def test_render_full_size_sampled_blob100k():
     """the benchmark's render launch (100k primitives, 512^2 pinhole, 8 spp,
-    single scattering, 8x8 tiles), repeated with 8 seeds, checked in mean on
-    a seeded sample of pixels the oracle renders one by one"""
+    single scattering with closed-form shadow transmittance, 8x8 tiles whose
+    shadow rays share a direction per sample and trace as packets),
+    repeated with 8 seeds, checked in mean on a seeded sample of pixels (in
+    distinct tiles) that the oracle renders one by one with ratio-tracked
+    shadow rays"""
     gf = require_gpu()
     params, rays, rho = W.scene("blob100k"), W.rays("blob100k"), W.rho("blob100k")
     scene = gf.Scene(dev(params), rho=rho)
     drays = dev(rays)
     sub = W.pixel_subset(rays.shape[0], k=24, seed=17)
+    tiles = (sub // 512 // 8) * 64 + (sub % 512) // 8
+    assert len(set(tiles.tolist())) == len(sub)
     runs = 8
     Lsum, Lv_sum = np.zeros(len(sub)), np.zeros(len(sub))
     for seed in range(runs):
-        d = gf.render_desc(spp=8, multiple=False, albedo=0.9, seed=1234 + seed)
+        d = gf.render_desc(spp=8, multiple=False, albedo=0.9, seed=1234 + seed, exact_shadow=True)
         L, Lv, _, _ = gf.gf_render_rays(scene, drays, d, image_width=512)
         Lsum += host(L)[sub]
         Lv_sum += host(Lv)[sub]
