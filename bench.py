@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--bin", default="mixture", help="orientation-bin strategy of the multiple-scattering workload")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="1M multiple-scattering workload: render only this many central rows (0: the full frame)")
     ap.add_argument("--ratio-shadow", action="store_true",
                     help="ratio-tracked shadow transmittance (default: closed form exp(-tau))")
     return ap.parse_args()
@@ -163,21 +165,28 @@ def main():
     value = units / (ms_per_step * 1e-3) / 1e6
 
     # algorithmic work of the timed launches: optical depth counted exactly on
-    # the same launch; the render's work per sample counted on every 16th
-    # pixel row (the counting variant walks a point query per consumed
-    # tentative point, which takes ~25x the render) and scaled to the frame
+    # the same launch; the render's work per sample counted with one sample
+    # per ray on every 4th pixel row (the counting variant walks a point query
+    # per consumed tentative point, far slower than the render; samples are
+    # independent, so the work per sample does not depend on their number)
+    # and scaled to the frame's rays and samples
     scene = gf.Scene(params, rho)
     masks, bits = masks_for(scene)
     tau_bytes, ren_bytes, ren_counts = [], [], []
-    stride = 16
+    stride = 4
     sub_rays = rays.view(width, width, 8)[::stride].reshape(-1, 8).contiguous()
+
+    def count_desc(mask):
+        d = desc(mask)
+        d.spp = 1
+        return d
     for k, m in enumerate(masks):
         log("counting work of mask %s" % mask_names[k])
         nodes, hits = gf.gf_optical_depth_counts(scene, rays, m, image_width=width)
         nn, nh = int(nodes.sum().item()), int(hits.sum().item())
         tau_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + PRIM_BYTES * nh + NODE_BYTES * nn)
         if args.render:
-            c = [v * stride for v in gf.gf_render_counts(scene, sub_rays, desc(m), image_width=0)]
+            c = [v * stride * args.spp for v in gf.gf_render_counts(scene, sub_rays, count_desc(m), image_width=width)]
             ren_counts.append(c)
             ren_bytes.append(npix * (RAY_BYTES + OUT_BYTES) + NODE_BYTES * c[5] + PRIM_BYTES * c[6])
         else:
@@ -302,6 +311,9 @@ def multiple_scattering_bench(args):
     name, spp = args.workload, 4
     params_h, rays_h, rho = W.scene(name), W.rays(name), W.rho(name)
     width = int(math.isqrt(rays_h.shape[0]))
+    rows = args.rows if 0 < args.rows < width else width
+    r0 = (width - rows) // 2
+    rays_h = np.ascontiguousarray(rays_h[r0 * width:(r0 + rows) * width])
     params, rays = torch.as_tensor(params_h).cuda(), torch.as_tensor(rays_h).cuda()
     npix = rays.shape[0]
     desc = gf.render_desc(spp=spp, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, env=1.0, stochastic=True,
@@ -334,21 +346,24 @@ def multiple_scattering_bench(args):
     ren_ms = float(np.mean([c.elapsed_time(d) for a, b, c, d in rec]))
     L, _, Tm, Tv = (x.cpu().numpy() for x in out)
     units = npix * (1 + spp)
-    # work per sample on the central band (the counting variant also walks
-    # a point query per consumed point)
+    # work per sample counted with one sample per ray on every 16th row
+    # (the counting variant walks a point query per consumed point, far
+    # slower than the render), scaled to the frame's rays and samples
     scene = gf.Scene(params, rho)
-    r0 = width // 2 - 32
-    band = rays[r0 * width:(r0 + 64) * width].contiguous()
-    log("counting work on a 64-row band")
-    c = gf.gf_render_counts(scene, band, desc, image_width=width)
-    band_samples = band.shape[0] * spp
-    alg_frame = npix * (RAY_BYTES + OUT_BYTES) + (NODE_BYTES * c[5] + PRIM_BYTES * c[6]) * (npix / band.shape[0])
+    band = rays.view(rows, width, 8)[::16].reshape(-1, 8).contiguous()
+    cdesc = gf.render_desc(spp=1, multiple=True, max_scatter=16, albedo=0.9, hg_g=0.3, env=1.0, stochastic=True,
+                           level="uniform_cv", bin=args.bin, seed=4321)
+    log("counting work on every 16th row (%d rays, 1 spp)" % band.shape[0])
+    c = gf.gf_render_counts(scene, band, cdesc, image_width=width)
+    log("counting done")
+    band_samples = band.shape[0]
+    alg_frame = npix * (RAY_BYTES + OUT_BYTES) + (NODE_BYTES * c[5] + PRIM_BYTES * c[6]) * (npix * spp / band_samples)
     ach = alg_frame / (ren_ms * 1e-3) / 1e9
     prof = profile_figures(name, "render")
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": prof.get("traffic"), "kernel": KERNELS["render"],
                 "algorithmic_bytes_per_launch": int(alg_frame), "launch_ms": round(ren_ms, 3),
-                "note": "algorithmic bytes counted on the central 64 rows, scaled to the frame"}
+                "note": "algorithmic bytes counted at 1 spp on every 16th row, scaled to the frame"}
     if prof.get("traffic"):
         roofline["measured_frac"] = round(prof["traffic"] / (ren_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
     if prof.get("valu_insts"):
@@ -359,9 +374,10 @@ def multiple_scattering_bench(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 1),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 (f64 geometry setup)",
         "data": "synthetic",
-        "config": {"workload": "%s: %s, %dx%d pinhole, %d spp, multiple scattering (HG 0.3, albedo 0.9, <= 16 "
+        "config": {"workload": "%s: %s, %dx%d pinhole%s, %d spp, multiple scattering (HG 0.3, albedo 0.9, <= 16 "
                                "bounces), per-segment stochastic masks (uniform+CV levels, %s bins)"
-                               % (name, W.describe(name), width, width, spp, args.bin),
+                               % (name, W.describe(name), width, width,
+                                  "" if rows == width else " (the central %d rows)" % rows, spp, args.bin),
                    "global_batch": npix, "parallelism": "single GPU"},
         "roofline": roofline,
         "build_ms": round(build_ms, 2), "tau_ms": round(tau_ms, 2), "tau_Mrays_s": round(npix / tau_ms / 1e3, 2),
