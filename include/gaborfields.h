@@ -257,9 +257,14 @@ typedef struct {
  * Outputs (device n, variances / T may be NULL): L mean / variance over spp,
  * primary-segment transmittance mean / variance.  image_width as for
  * gf_optical_depth.  Each ray's samples are traced by one lane with random
- * streams keyed by (seed, ray index, sample), so a ray's result depends on
- * its index in the launch but not on which rays are traced beside it.  The
- * call allocates its tracking workspace stream-ordered. */
+ * streams keyed by (seed, ray index, sample), so in a ray list a ray's
+ * result depends on its index but not on which rays are traced beside it.
+ * In an image launch (image_width > 0) the shadow directions of single
+ * scattering with closed-form transmittance come from the stream of the
+ * ray's 8x8 pixel tile (seed, tile, sample), shared by the tile's rays:
+ * every ray's estimate stays unbiased and the tile's shadow segments trace
+ * as one packet; a tile's result then depends on the tile only.  The call allocates its
+ * tracking workspace stream-ordered. */
 gf_status gf_render_rays(gf_scene scene, const float* rays, int64_t n, int image_width, const gf_render_desc* desc,
                          float* L_mean, float* L_var, float* T_mean, float* T_var, void* stream);
 

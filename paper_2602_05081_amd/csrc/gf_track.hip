@@ -1594,6 +1594,7 @@ gf_status gf_serve_fill_req(const gf_request* q, const float* rays, void* out_de
     d->S = gf_scene_view(q->scene);
     d->M = gf_mask_view(q->render.mask);
     d->A = render_args(&q->render);
+    d->A.tile_w = q->camera.width % 8 == 0 ? q->camera.width : 0;  // as gf_render: the same image
     d->rays = rays;
     d->out = q->out;
     d->n = q->camera.width * q->camera.height;

@@ -44,7 +44,7 @@ def test_server_mix_equals_alone_and_plain():
         plain, _ = gf.gf_render(scenes[r["scene"]], cam, desc, ws)
         assert torch.equal(mix[k], plain.view(-1)), k
         rays = gf.gf_camera_rays(cam)
-        listed, _, _, _ = gf.gf_render_rays(scenes[r["scene"]], rays, desc)
+        listed, _, _, _ = gf.gf_render_rays(scenes[r["scene"]], rays, desc, image_width=cam.width)
         assert torch.equal(mix[k], listed), k
         assert torch.isfinite(mix[k]).all()
 

@@ -277,7 +277,7 @@ def test_camera_render_in_caller_workspace():
     ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
     rad, T = gf.gf_render(scene, cam, d, ws[:need])
     rays = gf.gf_camera_rays(cam)
-    L, _, Tr, _ = gf.gf_render_rays(scene, rays, d)
+    L, _, Tr, _ = gf.gf_render_rays(scene, rays, d, image_width=48)
     assert torch.equal(rad.view(-1), L) and torch.equal(T.view(-1), Tr)
     with pytest.raises(gf.GfError):
         gf.gf_render(scene, cam, d, ws[:need - 256])
