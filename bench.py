@@ -57,7 +57,9 @@ def parse():
     ap.add_argument("--spp", type=int, default=8)
     ap.add_argument("--no-render", dest="render", action="store_false",
                     help="leave the single-scattering render out of the step (optical depth only)")
-    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="add the serving trace (continuous batching vs plain renderer; ~10 minutes)")
+    ap.add_argument("--no-serving", action="store_true", help="(default) no serving trace")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--serving-sweep", action="store_true", help="serving at 0.35, 0.7, 1.0, 1.4 x saturation")
@@ -237,7 +239,7 @@ def main():
         "build_ms": round(float(np.mean(timings["build"])), 3),
     }
 
-    if not args.no_serving:
+    if args.serving and not args.no_serving:
         log("serving trace")
         result["serving"] = serving(args, gf, W, np, torch)
     if not args.no_cpu:

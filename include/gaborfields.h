@@ -256,15 +256,18 @@ typedef struct {
  * escape; a collision after max_scatter scatterings ends the path with 0.
  * Outputs (device n, variances / T may be NULL): L mean / variance over spp,
  * primary-segment transmittance mean / variance.  image_width as for
- * gf_optical_depth.  Each ray's samples are traced by one lane with random
+ * gf_optical_depth.  Each sample of a ray is traced by one lane with random
  * streams keyed by (seed, ray index, sample), so in a ray list a ray's
  * result depends on its index but not on which rays are traced beside it.
  * In an image launch (image_width > 0) the shadow directions of single
  * scattering with closed-form transmittance come from the stream of the
  * ray's 8x8 pixel tile (seed, tile, sample), shared by the tile's rays:
  * every ray's estimate stays unbiased and the tile's shadow segments trace
- * as one packet; a tile's result then depends on the tile only.  The call allocates its
- * tracking workspace stream-ordered. */
+ * as one packet; a tile's result then depends on the tile only.  The
+ * samples of 64 rays may be spread over several work units (waves), their
+ * values stored and summed in sample order afterwards: the result has the
+ * same bits as one lane summing them.  The call allocates its tracking
+ * workspace (and that per-sample storage) stream-ordered. */
 gf_status gf_render_rays(gf_scene scene, const float* rays, int64_t n, int image_width, const gf_render_desc* desc,
                          float* L_mean, float* L_var, float* T_mean, float* T_var, void* stream);
 
@@ -292,7 +295,10 @@ typedef struct {
 gf_status gf_camera_rays(const gf_camera* cam, float* rays, void* stream);
 
 /* Bytes of caller-owned device workspace gf_render needs for this camera and
- * description (the camera rays plus the tracking lanes' state). */
+ * description: the camera rays, the tracking lanes' state and, where the
+ * render spreads each tile's samples over several work units, one L and one
+ * T value per pixel and sample (at most 1 GiB; beyond that the samples of a
+ * tile stay in one unit). */
 gf_status gf_render_workspace_size(gf_scene scene, const gf_camera* cam, const gf_render_desc* desc,
                                    size_t* bytes);
 
@@ -310,11 +316,13 @@ gf_status gf_render(gf_scene scene, const gf_camera* cam, const gf_render_desc* 
  * callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
  * file-scope device array of the library: the rays of up to 1,048,576
- * pixels and the tracking state of 1024 resident waves, about 100 MB that
- * each device the library runs on holds until the process ends.  A camera
- * with more pixels returns GF_EINVAL before any launch.  Outputs as
- * gf_render (radiance device height x width; primary_T device height x
- * width or NULL), bitwise the same.  Every call on one device shares the
+ * pixels, the tracking state of 1024 resident waves and 8,388,608 per-sample
+ * values (pixels x spp x 2; a render that needs more keeps each tile's
+ * samples in one work unit, which is slower on images with a few very
+ * dense tiles), about 130 MB that each device the library runs on holds
+ * until the process ends.  A camera with more pixels returns GF_EINVAL
+ * before any launch.  Outputs as gf_render (radiance device height x width;
+ * primary_T device height x width or NULL), bitwise the same.  Every call on one device shares the
  * array, which keeps the last call's contents: calls that overlap on one
  * device (other streams, other threads) race. */
 gf_status gf_render_noalloc(gf_scene scene, const gf_camera* cam, const gf_render_desc* desc, float* radiance,

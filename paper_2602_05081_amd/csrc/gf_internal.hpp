@@ -148,10 +148,14 @@ gf_status gf_zero_words(void* p, size_t words, hipStream_t sm);
 
 // host helpers of the render and serving code (gf_track.hip)
 gf_status gf_check_track_depth(const gf_scene_s* s, const char* who);
-// render of n rays with the tracking workspace ws (head + at least
-// min(max_waves, chunks) slices); outputs as gf_render
+// render of n rays with the tracking workspace ws (head + ws_waves slices;
+// the launch uses at most that many waves) and a per-sample buffer part of
+// part_cap floats (used when it holds gf_render_part_floats); outputs as
+// gf_render
+size_t gf_render_part_floats(const gf_render_desc* d, int64_t n, int tile_w);
 gf_status gf_render_launch_in(gf_scene s, const float* rays, int64_t n, int image_width, const gf_render_desc* d,
-                              float* ws, float* radiance, float* primary_T, hipStream_t sm, unsigned max_waves);
+                              float* ws, int64_t ws_waves, float* part, size_t part_cap, float* radiance,
+                              float* primary_T, hipStream_t sm);
 gf_status gf_camera_launch(const gf_camera* cam, float* rays, hipStream_t sm);
 gf_status gf_check_camera(const gf_camera* cam, const char* who);
 gf_status gf_check_render_desc(const gf_render_desc* d, const char* who);

@@ -9,7 +9,10 @@
 // file-scope device array: the camera rays of at most NOALLOC_MAX_PIXELS
 // pixels, then the tracking slices of NOALLOC_WAVES resident waves (the
 // render's waves loop over the image's chunks, so fewer resident waves than
-// chunks only costs time).  Each device holds its own copy for the life of
+// chunks only costs time), then NOALLOC_PART_FLOATS floats of per-sample
+// storage (a render whose samples need more keeps each chunk's samples in
+// one work unit: slower on images with a few very dense tiles, the same
+// bits).  Each device holds its own copy for the life of
 // the process; host code reaches it through the address hipGetSymbolAddress
 // returns on that device, kept per device.  Calls that overlap on one device
 // share the array and race.
@@ -17,7 +20,9 @@
 #define NOALLOC_MAX_PIXELS (1 << 20)
 #define NOALLOC_WAVES 1024
 #define NOALLOC_RAY_FLOATS ((size_t)NOALLOC_MAX_PIXELS * 8)
-#define NOALLOC_FLOATS (NOALLOC_RAY_FLOATS + (size_t)GF_TRACK_HEAD_FLOATS + (size_t)NOALLOC_WAVES * GF_TRACK_WAVE_FLOATS)
+#define NOALLOC_TRACK_FLOATS ((size_t)GF_TRACK_HEAD_FLOATS + (size_t)NOALLOC_WAVES * GF_TRACK_WAVE_FLOATS)
+#define NOALLOC_PART_FLOATS ((size_t)8 << 20)
+#define NOALLOC_FLOATS (NOALLOC_RAY_FLOATS + NOALLOC_TRACK_FLOATS + NOALLOC_PART_FLOATS)
 
 static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
 
@@ -59,6 +64,7 @@ extern "C" gf_status gf_render_noalloc(gf_scene s, const gf_camera* cam, const g
     const int tile_w = cam->width % 8 == 0 ? cam->width : 0;
     st = gf_camera_launch(cam, base, sm);
     if (st != GF_OK) return st;
-    return gf_render_launch_in(s, base, n, tile_w, d, base + NOALLOC_RAY_FLOATS, radiance, primary_T, sm,
-                               NOALLOC_WAVES);
+    return gf_render_launch_in(s, base, n, tile_w, d, base + NOALLOC_RAY_FLOATS, NOALLOC_WAVES,
+                               base + NOALLOC_RAY_FLOATS + NOALLOC_TRACK_FLOATS, NOALLOC_PART_FLOATS, radiance,
+                               primary_T, sm);
 }

@@ -272,13 +272,16 @@ def test_camera_render_in_caller_workspace():
     params, rho = W.scene("tiny256"), W.rho("tiny256")
     scene = gf.Scene(dev(params), rho=rho)
     cam = gf.camera(1, width=48, height=40)
-    d = gf.render_desc(spp=3, multiple=True, hg_g=0.3, seed=11)
-    need = gf.gf_render_workspace_size(scene, cam, d)
-    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
-    rad, T = gf.gf_render(scene, cam, d, ws[:need])
-    rays = gf.gf_camera_rays(cam)
-    L, _, Tr, _ = gf.gf_render_rays(scene, rays, d, image_width=48)
-    assert torch.equal(rad.view(-1), L) and torch.equal(T.view(-1), Tr)
+    # each tile's samples run as separate work units (more waves than
+    # tiles: the workspaces hold a slice per unit)
+    for d in (gf.render_desc(spp=3, multiple=True, hg_g=0.3, seed=11),
+              gf.render_desc(spp=8, exact_shadow=True, seed=12)):
+        need = gf.gf_render_workspace_size(scene, cam, d)
+        ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+        rad, T = gf.gf_render(scene, cam, d, ws[:need])
+        rays = gf.gf_camera_rays(cam)
+        L, _, Tr, _ = gf.gf_render_rays(scene, rays, d, image_width=48)
+        assert torch.equal(rad.view(-1), L) and torch.equal(T.view(-1), Tr)
     with pytest.raises(gf.GfError):
         gf.gf_render(scene, cam, d, ws[:need - 256])
     with pytest.raises(gf.GfError):
