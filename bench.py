@@ -311,6 +311,7 @@ def multiple_scattering_bench(args):
     from gen import workloads as W
 
     name, spp = args.workload, 4
+    KERNELS["render"] = "void k_render<false, 0>"  # delta tracking, ratio-tracked transmittances
     params_h, rays_h, rho = W.scene(name), W.rays(name), W.rho(name)
     width = int(math.isqrt(rays_h.shape[0]))
     rows = args.rows if 0 < args.rows < width else width
@@ -438,14 +439,14 @@ def serving(args, gf, W, np, torch):
     plain per-request renderer (FIFO, one request at a time, caller
     workspace).  The request rate is a multiple of the plain renderer's
     saturation rate on this trace (0.7 by default; --serving-sweep runs
-    several), and the server's memory budget (64 MB of camera rays, two
-    1024^2 requests) makes admission bind."""
+    several), and the server's memory budget (96 MB: two 1024^2 requests at
+    4 spp, rays and per-sample radiance) makes admission bind."""
     import gen
     from paper_2602_05081_amd import serve
     scenes = [gf.Scene(torch.as_tensor(W.scene(s)).cuda(), rho=W.rho(s)) for s in W.SERVE_SCENES]
     n = args.serving_requests
     reqs = gen.serving_requests(n, seed=5)
-    budget = 64 << 20
+    budget = 96 << 20
     # warm both paths
     serve.run_plain(scenes, reqs[:1], np.zeros(1))
     # saturation throughput of the plain renderer on this trace decides the rate

@@ -357,7 +357,9 @@ typedef struct {
 } gf_request;
 
 /* mem_budget: bytes of device workspace the admitted requests may hold at
- * once (each request holds width*height*32 bytes of rays while in flight).
+ * once (each request holds width*height*32 bytes of rays and
+ * width*height*spp*4 bytes of per-sample radiance, each 256 B aligned,
+ * while in flight).
  * tile_rays: rays per tile; max_tiles: tiles per device batch.  The server
  * also allocates, once, two batch slots, each with its own stream (default
  * priority) and tracking workspace (at most 3072 x 64 KB), so that a batch
@@ -366,15 +368,18 @@ typedef struct {
 gf_status gf_server_create(size_t mem_budget, int tile_rays, int max_tiles, void* stream, gf_server* out);
 gf_status gf_server_destroy(gf_server server);
 /* Queues a request (non-blocking); *id receives its id.  GF_EINVAL if it can
- * never fit the budget. */
+ * never fit the budget, or if max_tiles x tile_rays / 64 x spp reaches 2^30
+ * (work units a batch indexes). */
 gf_status gf_server_submit(gf_server server, const gf_request* req, uint64_t* id);
 /* Advances the scheduler: admits queued requests (FIFO) while memory allows,
  * launches the next batch of tiles from the admitted requests, shortest
  * remaining work first (rays left x samples, multiple scattering counted 3x),
  * on a free batch slot, and retires requests whose tiles have all completed.
  * At most two batches are in flight, on the two slot streams, overlapping.
- * The server renders delta-tracked requests (free_flight 0).  Non-blocking
- * unless `wait` != 0. */
+ * A batch's work units are single samples of 64 rays; each request's
+ * samples are stored and averaged per ray in sample order when the batch
+ * ends, so its image has the bits gf_render gives it.  The server renders
+ * delta-tracked requests (free_flight 0).  Non-blocking unless `wait` != 0. */
 gf_status gf_server_step(gf_server server, int wait);
 /* Retrieves up to max finished request ids (in completion order). */
 gf_status gf_server_poll(gf_server server, uint64_t* ids, int max, int* n_done);
@@ -385,7 +390,7 @@ gf_status gf_server_stats(gf_server server, int* queued, int* in_flight, size_t*
  * as they arrive).  Request i (host arrays of n entries: width, height, spp,
  * multiple != 0) arrives at arrival_s[i] (sorted ascending).  Each step
  * retires the batches whose end has passed, admits queued requests in
- * arrival order while width*height*32 bytes (256 B aligned) fit a first-fit
+ * arrival order while their pool bytes (as gf_server_create) fit a first-fit
  * pool of mem_budget bytes, and plans batches exactly as gf_server_step does
  * while fewer than two are in flight; a batch starts when the previous one
  * ends and takes sum over its tiles of rays x spp x (3 if multiple) divided

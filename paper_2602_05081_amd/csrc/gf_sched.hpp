@@ -62,10 +62,15 @@ struct Pool {
     }
 };
 
-// pool bytes of a request: its camera rays, 8 float32 per pixel
-static inline size_t request_bytes(int64_t width, int64_t height) {
-    size_t b = (size_t)(width * height) * 8 * sizeof(float);
-    return (b + kAlign - 1) / kAlign * kAlign;
+static inline size_t align_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+// pool bytes of a request: its camera rays (8 float32 per pixel), then one
+// float32 radiance per pixel and sample
+static inline size_t request_ray_bytes(int64_t width, int64_t height) {
+    return align_up((size_t)(width * height) * 8 * sizeof(float));
+}
+static inline size_t request_bytes(int64_t width, int64_t height, int64_t spp) {
+    return request_ray_bytes(width, height) + align_up((size_t)(width * height * spp) * sizeof(float));
 }
 
 struct SchedReq {

@@ -3,7 +3,8 @@
 //
 // Memory: the server owns one device pool of `mem_budget` bytes, carved by a
 // first-fit allocator; an admitted request holds width*height*32 bytes of
-// camera rays there until its last tile completes.  No device allocation
+// camera rays and width*height*spp*4 bytes of per-sample radiance there
+// until its last tile completes.  No device allocation
 // happens while serving; the tracking workspaces of the two batch slots are
 // allocated with the server.
 // Scheduling: requests wait in FIFO order until their rays fit the pool; an
@@ -11,7 +12,9 @@
 // caller's stream).  Each step assembles one batch of up to `max_tiles`
 // tiles of `tile_rays` rays from the admitted requests, shortest remaining
 // work first (rays left x samples, multiple scattering weighted 3x), and
-// launches it as a single kernel.  Two batch slots, each with its own
+// launches it as a single kernel whose work units are single samples of 64
+// rays (a chunk's samples on different waves), followed by the per-ray
+// means of the batch's tiles.  Two batch slots, each with its own
 // stream (default priority), workspace and event, let a batch start while
 // the previous one drains its last chunks; each slot stream first waits for
 // the ray generation queued before its launch.  A request finishes when the
@@ -27,10 +30,12 @@
 #include "gf_internal.hpp"
 #include "gf_sched.hpp"
 
-gf_status gf_serve_fill_req(const gf_request* q, const float* rays, void* out_desc);
+gf_status gf_serve_fill_req(const gf_request* q, const float* rays, float* part, void* out_desc);
 size_t gf_serve_req_size();
 size_t gf_serve_tile_size();
-gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int tile_rays, float* ws, hipStream_t sm);
+int gf_serve_tile_threads();
+gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int nunits, int tile_rays,
+                          int max_tiles, float* ws, hipStream_t sm);
 size_t gf_serve_workspace_bytes(int max_tiles, int tile_rays);
 
 namespace {
@@ -153,7 +158,11 @@ extern "C" gf_status gf_server_submit(gf_server S, const gf_request* q, uint64_t
         return gf_fail(GF_EINVAL, "gf_server_submit: the server batches delta-tracked renders with ratio-tracked "
                                   "transmittance only (free_flight 0, transmittance 0)");
     if (q->scene->depth > 64) return gf_fail(GF_EINVAL, "gf_server_submit: scene LBVH deeper than 64");
-    size_t bytes = gfs::request_bytes(q->camera.width, q->camera.height);
+    const int64_t chunks = (int64_t)S->max_tiles * ((S->tile_rays + gf_serve_tile_threads() - 1) / gf_serve_tile_threads());
+    if (chunks * q->render.spp > (int64_t)INT32_MAX / 2)
+        return gf_fail(GF_EINVAL, "gf_server_submit: %d samples per ray exceed what a batch of %d tiles can index",
+                       q->render.spp, S->max_tiles);
+    size_t bytes = gfs::request_bytes(q->camera.width, q->camera.height, q->render.spp);
     if (bytes > S->mem.budget)
         return gf_fail(GF_EINVAL, "gf_server_submit: request needs %zu bytes, budget %zu", bytes, S->mem.budget);
     Req* r = new Req();
@@ -225,6 +234,7 @@ static gf_status launch_batch(gf_server_s* S) {
     b.slot = slot;
     b.ev = S->events[slot];
     int ntiles = 0, nreq = 0;
+    int64_t nunits = 0;
     std::map<uint64_t, int> rays_in;
     for (const gfs::TileRef& t : plan) {
         const Req* r = static_cast<const Req*>(t.r);
@@ -233,11 +243,14 @@ static gf_status launch_batch(gf_server_s* S) {
         if (it == local.end()) {
             li = nreq++;
             local[r->id] = li;
-            gf_serve_fill_req(&r->q, (const float*)(S->pool + r->off), hreq + li * gf_serve_req_size());
+            gf_serve_fill_req(&r->q, (const float*)(S->pool + r->off),
+                              (float*)(S->pool + r->off + gfs::request_ray_bytes(r->q.camera.width, r->q.camera.height)),
+                              hreq + li * gf_serve_req_size());
         } else {
             li = it->second;
         }
-        int tile[4] = {li, t.first, t.count, 0};
+        int tile[4] = {li, t.first, t.count, (int)nunits};
+        nunits += (int64_t)((t.count + gf_serve_tile_threads() - 1) / gf_serve_tile_threads()) * r->spp;
         memcpy(htile + ntiles * gf_serve_tile_size(), tile, sizeof(tile));
         rays_in[r->id] += t.count;
         ++ntiles;
@@ -248,7 +261,8 @@ static gf_status launch_batch(gf_server_s* S) {
     GF_HIP(hipStreamWaitEvent(sm, S->rays_ready, 0));
     GF_HIP(hipMemcpyAsync(S->dreq[slot], hreq, gf_serve_req_size() * nreq, hipMemcpyHostToDevice, sm));
     GF_HIP(hipMemcpyAsync(S->dtile[slot], htile, gf_serve_tile_size() * ntiles, hipMemcpyHostToDevice, sm));
-    gf_status st = gf_serve_launch(S->dreq[slot], S->dtile[slot], ntiles, S->tile_rays, S->ws[slot], sm);
+    gf_status st = gf_serve_launch(S->dreq[slot], S->dtile[slot], ntiles, (int)nunits, S->tile_rays, S->max_tiles,
+                                   S->ws[slot], sm);
     if (st != GF_OK) return st;
     GF_HIP(hipEventRecord(b.ev, sm));
     S->slot_busy[slot] = true;
@@ -320,7 +334,7 @@ extern "C" gf_status gf_server_simulate(size_t mem_budget, int tile_rays, int ma
         r.n = width[i] * height[i];
         r.spp = spp[i];
         r.multiple = multiple[i] != 0;
-        r.bytes = gfs::request_bytes(width[i], height[i]);
+        r.bytes = gfs::request_bytes(width[i], height[i], spp[i]);
         r.off = 0;
         r.next_ray = r.rays_done = 0;
         if (r.bytes > mem.budget)

@@ -972,8 +972,9 @@ struct RenderArgs {
     uint32_t shadow_cells;  // 0: shadow segments draw their own mask
     int tile_w;             // image width of the launch's 8x8 tiles (0: a ray list)
     int su, groups;         // samples per work unit; units per chunk of 64 rays (groups * su >= spp)
-    int n;                  // rays of the launch
-    float* part;            // groups > 1: per-sample L (spp x n), then per-sample T (spp x n); else NULL
+    int n;                  // rays of the launch (of the request, when serving)
+    float* part;            // split samples: per-sample L (spp x n), then per-sample T (spp x n) if keep_T; else NULL
+    int keep_T;
     uint64_t seed;
 };
 
@@ -1270,10 +1271,10 @@ struct RenderLane {
     // after the camera segment: its transmittance estimate (summed, or
     // stored for the reduction when the ray's samples are split)
     __device__ void camera_done(const RenderArgs& A) {
-        if (A.part)
-            A.part[((size_t)A.spp + cs) * A.n + key] = st.T;
-        else
+        if (!A.part)
             acc.add_T(st.T);
+        else if (A.keep_T)
+            A.part[((size_t)A.spp + cs) * A.n + key] = st.T;
     }
     // the rest of sample s from its camera outcome (collision distance tc,
     // weight factor wf); true when the sample is already over
@@ -1581,10 +1582,14 @@ __global__ __launch_bounds__(256) void k_render_reduce(const float* __restrict__
 }
 
 // Serving: one launch renders tiles of many requests (each tile a contiguous
-// range of one request's rays, cut into chunks of 64).  A request's random
-// streams are keyed by its own seed and pixel index and a lane's result does
-// not depend on the other rays of its chunk, so its image does not depend on
-// the batch.
+// range of one request's rays, cut into chunks of 64).  A work unit is one
+// sample of one chunk: the units of tile t start at tiles[t].unit0, chunk by
+// chunk, the request's samples of a chunk next to each other.  Every sample's
+// L goes to the request's per-sample buffer (spp x n floats) and
+// k_serve_reduce sums a tile's samples once the launch is over.  A request's
+// random streams are keyed by its own seed and pixel index and a lane's
+// result does not depend on the other rays of its chunk, so its image does
+// not depend on the batch.
 struct ServeReq {
     SceneView S;
     MaskView M;
@@ -1595,24 +1600,57 @@ struct ServeReq {
 };
 
 struct ServeTile {
-    int req, first, count, pad;
+    int req, first, count, unit0;
 };
 
+// the tile holding unit u (tiles in unit order)
+static __device__ __forceinline__ int serve_tile_of(const ServeTile* __restrict__ tiles, int ntiles, int u) {
+    int lo = 0, hi = ntiles - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tiles[mid].unit0 <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(TR_THREADS) void k_render_tiles(const ServeReq* __restrict__ reqs,
-                                                             const ServeTile* __restrict__ tiles, int chunks_per_tile,
-                                                             int nchunks, float* __restrict__ ws) {
+                                                             const ServeTile* __restrict__ tiles, int ntiles,
+                                                             int nunits, float* __restrict__ ws) {
     LANE_MEM(ws + WS_HEAD)
     __shared__ int pstk[TR_STACK];
     Work wk{};
-    for (int c = next_chunk((unsigned*)ws); c < nchunks; c = next_chunk((unsigned*)ws)) {
-        const ServeTile tl = tiles[c / chunks_per_tile];
+    for (int u = next_chunk((unsigned*)ws); u < nunits; u = next_chunk((unsigned*)ws)) {
+        const ServeTile tl = tiles[serve_tile_of(tiles, ntiles, u)];
         const ServeReq& R = reqs[tl.req];
-        int local = (c % chunks_per_tile) * TR_THREADS + (int)threadIdx.x;
-        int idx = local < tl.count ? tl.first + local : -1;
+        const int v = u - tl.unit0, chunk = v / R.A.spp, smp = v - chunk * R.A.spp;
+        const int local = chunk * TR_THREADS + (int)threadIdx.x;
+        const int idx = local < tl.count ? tl.first + local : -1;
         float o[4];
-        render_rays<false, 0>(R.S, R.M, R.A, R.rays, idx, 0, R.A.spp, lm, pstk, wk, o);
-        if (idx >= 0) R.out[idx] = o[0];
+        render_rays<false, 0>(R.S, R.M, R.A, R.rays, idx, smp, smp + 1, lm, pstk, wk, o);
     }
+}
+
+// mean radiance of every ray of a launch's tiles from the stored samples
+// (one thread per ray slot of tile_rays per tile)
+__global__ __launch_bounds__(256) void k_serve_reduce(const ServeReq* __restrict__ reqs,
+                                                      const ServeTile* __restrict__ tiles, int tile_rays,
+                                                      int64_t nslots) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nslots) return;
+    const ServeTile tl = tiles[i / tile_rays];
+    const int local = (int)(i % tile_rays);
+    if (local >= tl.count) return;
+    const ServeReq& R = reqs[tl.req];
+    const int idx = tl.first + local, spp = R.A.spp;
+    SampleSums a;
+    a.zero();
+    for (int s = 0; s < spp; ++s) a.add_L(R.A.part[(size_t)s * R.n + idx]);
+    float o[4];
+    a.result(spp, o);
+    R.out[idx] = o[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1648,11 +1686,12 @@ static RenderArgs render_args(const gf_render_desc* d) {
     A.groups = 1;
     A.n = 0;
     A.part = nullptr;
+    A.keep_T = 1;
     A.seed = d->seed;
     return A;
 }
 
-gf_status gf_serve_fill_req(const gf_request* q, const float* rays, void* out_desc) {
+gf_status gf_serve_fill_req(const gf_request* q, const float* rays, float* part, void* out_desc) {
     ServeReq* d = (ServeReq*)out_desc;
     d->S = gf_scene_view(q->scene);
     d->M = gf_mask_view(q->render.mask);
@@ -1661,6 +1700,9 @@ gf_status gf_serve_fill_req(const gf_request* q, const float* rays, void* out_de
     d->rays = rays;
     d->out = q->out;
     d->n = q->camera.width * q->camera.height;
+    d->A.n = d->n;
+    d->A.part = part;  // spp x n per-sample radiance
+    d->A.keep_T = 0;
     return GF_OK;
 }
 
@@ -1673,12 +1715,17 @@ size_t gf_serve_workspace_bytes(int max_tiles, int tile_rays) {
     return gf_track_workspace_bytes((int64_t)max_tiles * bpt);
 }
 
-gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int tile_rays, float* ws,
-                          hipStream_t sm) {
-    int bpt = (tile_rays + TR_THREADS - 1) / TR_THREADS;
+// A batch of ntiles tiles (nunits work units) in the workspace ws of a
+// server created with max_tiles, then the per-ray means.
+gf_status gf_serve_launch(const void* dreqs, const void* dtiles, int ntiles, int nunits, int tile_rays,
+                          int max_tiles, float* ws, hipStream_t sm) {
+    const int64_t bpt = (tile_rays + TR_THREADS - 1) / TR_THREADS;
+    const unsigned g = std::min(res_blocks(nunits), res_blocks((int64_t)max_tiles * bpt));
     k_zero<<<1, 1, 0, sm>>>((unsigned*)ws);
-    k_render_tiles<<<res_blocks((int64_t)ntiles * bpt), TR_THREADS, 0, sm>>>(
-        (const ServeReq*)dreqs, (const ServeTile*)dtiles, bpt, ntiles * bpt, ws);
+    k_render_tiles<<<g, TR_THREADS, 0, sm>>>((const ServeReq*)dreqs, (const ServeTile*)dtiles, ntiles, nunits, ws);
+    const int64_t slots = (int64_t)ntiles * tile_rays;
+    k_serve_reduce<<<(unsigned)((slots + 255) / 256), 256, 0, sm>>>((const ServeReq*)dreqs, (const ServeTile*)dtiles,
+                                                                    tile_rays, slots);
     GF_HIP(hipGetLastError());
     return GF_OK;
 }

@@ -27,8 +27,10 @@ def test_server_mix_equals_alone_and_plain():
     scenes = [gf.Scene(dev(gen.blob_scene(n, s)), rho=r) for n, s, r in
               ((2000, 10, 0.004), (8000, 11, 0.0015), (20000, 12, 0.0008))]
     reqs = _trace(24, 3)
-    budget = 48 * 48 * 32 * 3  # a few requests at a time: admission binds
-    budget = max(budget, 96 * 96 * 32)
+    # a few requests at a time: admission binds (pool bytes: rays, then
+    # per-sample radiance)
+    need = [r["res"] ** 2 * (32 + 4 * r["spp"]) + 512 for r in reqs]
+    budget = max(3 * 48 * 48 * (32 + 16) + 1536, max(need))
     arrivals = np.zeros(len(reqs))
     lat, mk, mix, held = serve.run_server(scenes, reqs, arrivals, mem_budget=budget, tile_rays=512, max_tiles=8,
                                           time_limit=120)
@@ -53,7 +55,7 @@ def test_server_rejects_oversized_request():
     gf = require_gpu()
     from paper_2602_05081_amd import serve
     scene = gf.Scene(dev(gen.blob_scene(500, 1)), rho=0.01)
-    srv = gf._lib.Server(64 * 64 * 32, 256, 4)
+    srv = gf._lib.Server(64 * 64 * 32 + 64 * 64 * 4, 256, 4)
     r = dict(scene=0, res=128, lod=0, spp=1, multiple=0, az=0.0, el=0.0, seed=1)
     out = torch.empty(128 * 128, device="cuda")
     with pytest.raises(gf.GfError):

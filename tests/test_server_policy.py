@@ -7,7 +7,14 @@ traces check the invariants."""
 import numpy as np
 import pytest
 
-B64 = 64 * 64 * 32  # pool bytes of a 64x64 request (8 float32 rays per pixel)
+def req_bytes(w, h, spp):
+    """pool bytes of a request: 8 float32 rays per pixel, then one float32
+    radiance per pixel and sample, each part 256-byte aligned"""
+    up = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    return up(w * h * 32) + up(w * h * spp * 4)
+
+
+B64 = req_bytes(64, 64, 1)  # a 64x64 request at 1 spp
 
 
 @pytest.fixture(scope="module")
@@ -17,13 +24,14 @@ def sim():
 
 
 def test_budget_binds_and_admission_is_fifo(sim):
-    # room for two 64x64 requests; one tile per batch; 4096 ray-samples per second
-    admit, done, held = sim(2 * B64, 4096, 1, [64] * 3, [64] * 3, [1, 2, 1], [0, 0, 0], [0.0, 0.0, 0.0], 4096.0)
+    # room for the first two 64x64 requests; one tile per batch; 4096 ray-samples per second
+    budget = req_bytes(64, 64, 1) + req_bytes(64, 64, 2)
+    admit, done, held = sim(budget, 4096, 1, [64] * 3, [64] * 3, [1, 2, 1], [0, 0, 0], [0.0, 0.0, 0.0], 4096.0)
     # t=0: A and B admitted, batches A (ends 1) and B (ends 3); t=1: A done,
     # C admitted, its batch runs after B's (ends 4)
     assert list(admit) == [0.0, 0.0, 1.0]
     assert list(done) == [1.0, 3.0, 4.0]
-    assert held == 2 * B64
+    assert held == budget
 
 
 def test_least_remaining_work_first(sim):
