@@ -79,7 +79,7 @@ static int plan_checks(unsigned seed) {
         r.n = 1 + (int)(g() % 70000);
         r.spp = 1 + (int)(g() % 4);
         r.multiple = (g() & 1) != 0;
-        r.bytes = gfs::request_bytes(r.n, 1);
+        r.bytes = gfs::request_bytes(r.n, 1, r.spp);
         r.off = 0;
         r.next_ray = r.rays_done = 0;
         active.push_back(&r);
