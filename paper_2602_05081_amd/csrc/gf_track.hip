@@ -58,9 +58,9 @@
 
 // Workspace rows of a wave (each row: TR_THREADS lanes x 4 B); the slice
 // size is published to the other translation units as
-// GF_TRACK_WAVE_FLOATS.
-#define WS_KAP 0
-#define WS_MAJ TK
+// GF_TRACK_WAVE_FLOATS.  Rows [WS_KM, WS_KM + 2 TK) hold (kappa, mu) of the
+// TK points as float2, point k of lane l at float2 index k TR_THREADS + l.
+#define WS_KM 0
 #define WS_XI (2 * TK)
 #define WS_SPILL (3 * TK)
 #define WS_TC (WS_SPILL + TR_STACK - TS_LDS)
@@ -316,10 +316,10 @@ struct LaneMem {
     float* t;   // LDS, TK tentative distances (or CDF bins), stride TR_THREADS
     float* cw;  // LDS, GF_NCELLS cell weights of the current segment, stride TR_THREADS
     float* ws;  // workspace: row r at ws[r * TR_THREADS]
+    float2* km;  // workspace: (kappa, mu) of point k at km[k * TR_THREADS]
     __device__ float w(int c) const { return cw[c * TR_THREADS]; }
     __device__ float mw(int c) const { return fminf(cw[c * TR_THREADS], MAJ_CAP); }
-    __device__ float& kap(int k) const { return ws[(WS_KAP + k) * TR_THREADS]; }
-    __device__ float& maj(int k) const { return ws[(WS_MAJ + k) * TR_THREADS]; }
+    __device__ float2& kapmaj(int k) const { return km[k * TR_THREADS]; }
     __device__ float& xi(int k) const { return ws[(WS_XI + k) * TR_THREADS]; }
     __device__ float& ctc(int k) const { return ws[(WS_TC + k) * TR_THREADS]; }  // camera collision of sample k
     __device__ float& cwf(int k) const { return ws[(WS_WF + k) * TR_THREADS]; }  // its delta-tracking weight
@@ -344,7 +344,8 @@ struct LaneMem {
     lm.cand = cand_all + threadIdx.x;                                                   \
     lm.t = t_all + threadIdx.x;                                                         \
     lm.cw = cw_all + threadIdx.x;                                                       \
-    lm.ws = (ws_base) + (size_t)blockIdx.x * (WS_ROWS * TR_THREADS) + threadIdx.x;
+    lm.ws = (ws_base) + (size_t)blockIdx.x * (WS_ROWS * TR_THREADS) + threadIdx.x;             \
+    lm.km = (float2*)((ws_base) + (size_t)blockIdx.x * (WS_ROWS * TR_THREADS) + WS_KM * TR_THREADS) + threadIdx.x;
 
 // chord of primitive P with the ray in float32: false when M < r^2 misses
 // [ta, tb]; otherwise the clipped chord [ci, co], the closest-point parameter
@@ -600,18 +601,25 @@ static __device__ __forceinline__ void add_chord(const PrimF& P, const ChordF& C
                                                  const Seg& sg, int np, int k, const LaneMem& lm) {
     float am = P.amp * GF_NORM, aa = fabsf(am);
     float ws = copysignf(lm.w(P.cell), am);
+    // carrier phase (cycles) along the chord: its value at the closest
+    // point plus its slope times the distance from there
+    const float yx = sg.ox + C.tc * sg.vx - P.mux, yy = sg.oy + C.tc * sg.vy - P.muy,
+                yz = sg.oz + C.tc * sg.vz - P.muz;
+    const float thc = P.fx * yx + P.fy * yy + P.fz * yz + P.phi * (float)GF_INV_2PI;
+    const float dph = P.fx * sg.vx + P.fy * sg.vy + P.fz * sg.vz;
     for (; k < np; ++k) {
         float t = lm.t[k * TR_THREADS];
         if (t > C.co) break;
         float dt = t - C.tc;
         float e = __expf(-0.5f * (C.h2 + C.n2 * dt * dt));
-        float dx = sg.ox + t * sg.vx - P.mux, dy = sg.oy + t * sg.vy - P.muy, dz = sg.oz + t * sg.vz - P.muz;
-        float ph = P.fx * dx + P.fy * dy + P.fz * dz + P.phi * (float)GF_INV_2PI;
+        float ph = fmaf(dt, dph, thc);
         float sn, cs;
         sincos2pi(ph - rintf(ph), &sn, &cs);
         float ce = aa * e;
-        lm.kap(k) += ws * (ce * cs);
-        lm.maj(k) += mw * ce;
+        float2 v = lm.kapmaj(k);
+        v.x += ws * (ce * cs);
+        v.y += mw * ce;
+        lm.kapmaj(k) = v;
     }
 }
 
@@ -782,10 +790,7 @@ static __device__ __forceinline__ void eval_leaf(const SceneView& S, const MaskV
 // points sorted, kappa and mu cleared: ready for an evaluation pass
 static __device__ __forceinline__ void open_points(const LaneMem& lm, int np) {
     sort_points(lm, np);
-    for (int k = 0; k < np; ++k) {
-        lm.kap(k) = 0.0f;
-        lm.maj(k) = 0.0f;
-    }
+    for (int k = 0; k < np; ++k) lm.kapmaj(k) = make_float2(0.0f, 0.0f);
 }
 
 // Decisions of an evaluated window and the move to the next one.  Returns
@@ -852,11 +857,13 @@ static __device__ bool decide_window(const SceneView& S, const MaskView& M, SegS
         int used = np;
         if (!(st.mode & MODE_RATIO) && (st.mode & MODE_DELTA) && !(st.tc < INFINITY)) {
             float fr, fn;
-            for (int k = 0; k < np; ++k)
-                if (delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn)) {
+            for (int k = 0; k < np; ++k) {
+                const float2 v = lm.kapmaj(k);
+                if (delta_real(v.x, v.y, lm.xi(k), &fr, &fn)) {
                     used = k + 1;
                     break;
                 }
+            }
         }
         wk.used += used;
         for (int k = 0; k < used; ++k) {
@@ -866,13 +873,17 @@ static __device__ bool decide_window(const SceneView& S, const MaskView& M, SegS
         }
     }
     if (st.mode & MODE_RATIO)
-        for (int k = 0; k < np; ++k) st.T *= 1.0f - lm.kap(k) / lm.maj(k);
+        for (int k = 0; k < np; ++k) {
+            const float2 v = lm.kapmaj(k);
+            st.T *= 1.0f - v.x / v.y;
+        }
     if ((st.mode & MODE_DELTA) && !(st.tc < INFINITY)) {
         // the collision is the earliest real point; null factors of the
         // points before it apply
         float w = 1.0f, fr, fn;
         for (int k = 0; k < np; ++k) {
-            bool real = delta_real(lm.kap(k), lm.maj(k), lm.xi(k), &fr, &fn);
+            const float2 v = lm.kapmaj(k);
+            bool real = delta_real(v.x, v.y, lm.xi(k), &fr, &fn);
             if (real) {
                 w *= fr;
                 st.tc = lm.t[k * TR_THREADS];
@@ -944,15 +955,28 @@ static __device__ __forceinline__ int ray_of_tr(int gid, int n, int tile_w) {
     return py < height ? py * tile_w + px : -1;
 }
 
-// Order in which a launch hands out the chunks of an image: rows of 8x8
-// tiles from the middle of the image outward (middle row, the one above, the
-// one below, ...), so the dense centre, whose chunks take longest, starts
-// first and the launch does not end on a few slow chunks.  A bijection on
-// the chunk indices; a ray's result does not depend on when it is traced.
+// Order in which a launch hands out the chunks of an image: first the
+// central half of the columns of 8x8 tiles, then the outer columns, each
+// part by rows from the middle of the image outward (middle row, the one
+// above, the one below, ...), so the dense centre, whose chunks take
+// longest, starts first and the launch does not end on a few slow chunks.
+// A bijection on the chunk indices; a ray's result does not depend on when
+// it is traced.
 static __device__ __forceinline__ int tile_order(int c, int nchunks, int tile_w) {
     if (tile_w <= 0) return c;
     const int tiles_x = tile_w >> 3, tiles_y = nchunks / tiles_x;
-    const int q = c / tiles_x, tx = c - q * tiles_x, mid = tiles_y >> 1;
+    const int x0 = tiles_x >> 2, wa = tiles_x - 2 * x0, na = wa * tiles_y;
+    int q, tx;
+    if (c < na) {
+        q = c / wa;
+        tx = x0 + (c - q * wa);
+    } else {
+        const int wb = tiles_x - wa, c2 = c - na;
+        q = c2 / wb;
+        const int r = c2 - q * wb;
+        tx = r < x0 ? r : r + wa;
+    }
+    const int mid = tiles_y >> 1;
     const int ty = (q & 1) ? mid - ((q + 1) >> 1) : mid + (q >> 1);
     return ty * tiles_x + tx;
 }
@@ -1143,17 +1167,74 @@ static __device__ void exact_segment(const SceneView& S, const MaskView& M, SegS
     if (act) st.live = false;
 }
 
-// Exact transmittance exp(-tau) of a lane's own segment: one traversal
-// summing the closed-form integrals of the crossed chords (Sec. 4.4), the
-// way the tomography case of Sec. 4.6 turns optical depth into
-// transmittance.  Its mean equals that of ratio tracking, with no variance.
+// e^{-u^2/2} Re{e^{i psi(u)} w((sgn(u) Omega + i|u|)/sqrt 2)} in float32
+// (psi(u) = 2 pi (thc + u omc), phases in cycles)
+static __device__ __forceinline__ float tail_f32(float u, float Om, float thc, float omc) {
+    const float is2 = 0.70710678118654752440f;
+    const float sg = u < 0.0f ? -1.0f : 1.0f;
+    const float2 w = wofz_weideman(sg * Om * is2, fabsf(u) * is2, c_weid_tr, c_weidL_tr);
+    const float c = fmaf(u, omc, thc);
+    float sp, cp;
+    sincos2pi(c - rintf(c), &sp, &cp);
+    return __expf(-0.5f * u * u) * (cp * w.x - sp * w.y);
+}
+
+// Optical depth of primitive P over [ta, tb] of segment sg for the render's
+// closed-form transmittance exp(-sum): the segment integral of Sec. 4.4
+// (Re{e^{i theta} [E(u_b) - E(u_a)]}, Appendix A) with float32 chord
+// geometry and float32 Faddeeva evaluations, one branch-free form for every
+// hit.  Where the difference cancels (short or strongly oscillating chords)
+// its error stays near float32 rounding of the terms, an absolute error of
+// about 1e-7 of the primitive's peak contribution, far below the Monte Carlo
+// error of the radiance it enters; the optical-depth kernel keeps its
+// binary64 geometry, quadrature and binary64 fallbacks for its relative
+// bound.  False when the chord is empty; *tc: closest-point parameter.
+static __device__ __forceinline__ bool shadow_tau_f32(const PrimF& P, const Seg& sg, float ta, float tb, float* tau,
+                                                      float* tc_out) {
+    const float dx = sg.ox - P.mux, dy = sg.oy - P.muy, dz = sg.oz - P.muz;
+    const float avx = P.a00 * sg.vx + P.a01 * sg.vy + P.a02 * sg.vz;
+    const float avy = P.a01 * sg.vx + P.a11 * sg.vy + P.a12 * sg.vz;
+    const float avz = P.a02 * sg.vx + P.a12 * sg.vy + P.a22 * sg.vz;
+    const float a = sg.vx * avx + sg.vy * avy + sg.vz * avz;
+    const float tc = -(dx * avx + dy * avy + dz * avz) / a;
+    const float yx = dx + tc * sg.vx, yy = dy + tc * sg.vy, yz = dz + tc * sg.vz;
+    const float h2 = yx * (P.a00 * yx + P.a01 * yy + P.a02 * yz) + yy * (P.a01 * yx + P.a11 * yy + P.a12 * yz) +
+                     yz * (P.a02 * yx + P.a12 * yy + P.a22 * yz);
+    if (!(h2 < P.r2)) return false;
+    const float n = sqrtf(a), inv_n = 1.0f / n;
+    const float half = sqrtf(P.r2 - h2), hn = half * inv_n;
+    const float tin = tc - hn, tout = tc + hn;
+    const float lo = fmaxf(ta, tin), hi = fminf(tb, tout);
+    if (!(lo < hi)) return false;
+    const bool enda = !(ta > tin), endb = !(tb < tout);
+    const float thc = P.fx * yx + P.fy * yy + P.fz * yz + P.phi * (float)GF_INV_2PI;
+    const float omc = (P.fx * sg.vx + P.fy * sg.vy + P.fz * sg.vz) * inv_n;
+    const float Om = 2.0f * (float)GF_PI * omc;
+    const float eO = __expf(-0.5f * Om * Om);
+    float sth, cth;
+    sincos2pi(thc - rintf(thc), &sth, &cth);
+    float val;
+    if (enda && endb) {
+        // the whole chord: E(h) - E(-h) = 2 Re E(h)
+        val = 2.0f * cth * (eO - tail_f32(half, Om, 0.0f, omc));
+    } else {
+        const float ua = enda ? -half : n * (lo - tc), ub = endb ? half : n * (hi - tc);
+        const float sa = ua < 0.0f ? -1.0f : 1.0f, sb = ub < 0.0f ? -1.0f : 1.0f;
+        val = (sb - sa) * eO * cth - sb * tail_f32(ub, Om, thc, omc) + sa * tail_f32(ua, Om, thc, omc);
+    }
+    *tau = P.amp * inv_n * __expf(-0.5f * h2) * val;
+    *tc_out = tc;
+    return true;
+}
+
+// Closed-form transmittance exp(-tau) of a lane's own segment: one
+// traversal summing the closed-form integrals of the crossed chords
+// (Sec. 4.4, float32: shadow_tau_f32), the way the tomography case of
+// Sec. 4.6 turns optical depth into transmittance.  Its mean equals that of
+// ratio tracking, with no variance.
 template <bool COUNT>
 static __device__ void exact_T_own(const SceneView& S, const MaskView& M, SegState& st, const LaneMem& lm, Work& wk) {
     if (!st.live) return;
-    RayD R;
-    R.ox = st.sg.ox; R.oy = st.sg.oy; R.oz = st.sg.oz;
-    R.vx = st.sg.vx; R.vy = st.sg.vy; R.vz = st.sg.vz;
-    R.tmin = st.sg.ta; R.tmax = st.sg.tb;
     float acc = 0.0f;
     const Seg& sg = st.sg;
     lane_traverse<COUNT>(S, st.cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, sg.tb, lm, wk, [&](int j) {
@@ -1161,36 +1242,32 @@ static __device__ void exact_T_own(const SceneView& S, const MaskView& M, SegSta
         if (COUNT) ++wk.prims;
         const float w = lm.w(P.cell);
         if (w == 0.0f || !prim_on(M, P.orig)) return;
-        HitGeom H;
-        if (!hit_geom(P, R, S.A64 + (size_t)j * GF_A64, H)) return;
-        if (lod_drop(P, sg, (float)H.tc)) return;
-        acc += w * hit_value(P, H, c_weid_tr, c_weidL_tr, c_weid64_tr, c_weidL64_tr);
+        float tau, tc;
+        if (!shadow_tau_f32(P, sg, sg.ta, sg.tb, &tau, &tc)) return;
+        if (lod_drop(P, sg, tc)) return;
+        acc += w * tau;
     });
     st.T = __expf(-acc);
     st.live = false;
 }
 
-// Exact transmittance of the segments of a whole wave in one packet walk
+// Closed-form transmittance of the segments of a whole wave in one packet walk
 // (the rays of a tile's shadow segments share their direction, so the
 // packet stays coherent); every lane of the wave calls it.
 template <bool COUNT>
 static __device__ void exact_T_packet(const SceneView& S, const MaskView& M, SegState& st, bool act, const LaneMem& lm,
                                       int* pstk, Work& wk) {
     act = act && st.live;
-    RayD R;
-    R.ox = st.sg.ox; R.oy = st.sg.oy; R.oz = st.sg.oz;
-    R.vx = st.sg.vx; R.vy = st.sg.vy; R.vz = st.sg.vz;
-    R.tmin = st.sg.ta; R.tmax = st.sg.tb;
     float acc = 0.0f;
     packet_walk<COUNT>(S, st, act, st.sg.ta, st.sg.tb, pstk, wk, [&](int j) {
         PrimF P = load_prim(S.prims, j);
         if (COUNT) ++wk.prims;
         const float w = lm.w(P.cell);
         if (w == 0.0f || !prim_on(M, P.orig)) return;
-        HitGeom H;
-        if (!hit_geom(P, R, S.A64 + (size_t)j * GF_A64, H)) return;
-        if (lod_drop(P, st.sg, (float)H.tc)) return;
-        acc += w * hit_value(P, H, c_weid_tr, c_weidL_tr, c_weid64_tr, c_weidL64_tr);
+        float tau, tc;
+        if (!shadow_tau_f32(P, st.sg, st.sg.ta, st.sg.tb, &tau, &tc)) return;
+        if (lod_drop(P, st.sg, tc)) return;
+        acc += w * tau;
     });
     if (act) {
         st.T = __expf(-acc);
@@ -1528,8 +1605,10 @@ __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, c
 // with more, every sample's L and T go to A.part and k_render_reduce sums
 // them.  Splitting a chunk's samples over several waves keeps the chip busy
 // to the end of a launch whose few densest tiles cost far more than the rest.
+// At least two waves per SIMD: without the bound the CDF-inversion instance
+// takes more than 256 registers and runs one wave per SIMD.
 template <bool COUNT, int FF>
-__global__ __launch_bounds__(TR_THREADS) void k_render(SceneView S, MaskView M, const float* __restrict__ rays, int n,
+__global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_render(SceneView S, MaskView M, const float* __restrict__ rays, int n,
                                                        int tile_w, int nchunks, RenderArgs A, float* __restrict__ ws,
                                                        float* __restrict__ Lm, float* __restrict__ Lv,
                                                        float* __restrict__ Tm, float* __restrict__ Tv,
