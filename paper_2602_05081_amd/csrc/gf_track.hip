@@ -1605,10 +1605,12 @@ __global__ __launch_bounds__(TR_THREADS) void k_ratio(SceneView S, MaskView M, c
 // with more, every sample's L and T go to A.part and k_render_reduce sums
 // them.  Splitting a chunk's samples over several waves keeps the chip busy
 // to the end of a launch whose few densest tiles cost far more than the rest.
-// At least two waves per SIMD: without the bound the CDF-inversion instance
-// takes more than 256 registers and runs one wave per SIMD.
+// The CDF-inversion instance asks for at least two waves per SIMD: without
+// the bound it takes more than 256 registers and runs one wave per SIMD.
+// The other instances fit two waves without it, and the bound costs them
+// 7-10% (the register allocator then trades registers for reloads).
 template <bool COUNT, int FF>
-__global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(2))) void k_render(SceneView S, MaskView M, const float* __restrict__ rays, int n,
+__global__ __launch_bounds__(TR_THREADS) __attribute__((amdgpu_waves_per_eu(FF == 2 ? 2 : 1))) void k_render(SceneView S, MaskView M, const float* __restrict__ rays, int n,
                                                        int tile_w, int nchunks, RenderArgs A, float* __restrict__ ws,
                                                        float* __restrict__ Lm, float* __restrict__ Lv,
                                                        float* __restrict__ Tm, float* __restrict__ Tv,
