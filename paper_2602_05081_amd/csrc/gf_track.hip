@@ -14,19 +14,21 @@
 // leaves the chord's envelope as intensity.  One LBVH traversal proposes the
 // points, a second one evaluates kappa and mu at all of them.
 //
-// Windows.  A lane holds at most TK tentative points.  When a segment has
-// more, the buffer keeps the TK earliest and the window ends at the last of
-// them; the process is restarted just after it.  A Poisson process restarted
-// at one of its own points (a stopping time) is again Poisson, so each window
-// is an exact sample of the process restricted to it.
+// Windows.  A lane holds at most a window's capacity of tentative points
+// (TK, or fewer for the first windows of a segment that only seeks its
+// first collision).  When a segment has more, the buffer keeps the earliest
+// and the window ends at the last of them; the process is restarted just
+// after it.  A Poisson process restarted at one of its own points (a
+// stopping time) is again Poisson, so each window is an exact sample of the
+// process restricted to it.
 //
-// Lanes.  One ray per lane with all its samples.  Every lane of a wave runs
-// the same steps (proposal traversal, evaluation traversal, decision) in each
-// iteration of one flat loop, whatever its path length: a lane whose sample
-// ends starts its next sample in the next iteration, so waves stay converged.
-// All random numbers of a sample come from one counter-based stream keyed by
-// (seed, ray, sample); a ray's result does not depend on the other rays of
-// the launch.
+// Lanes.  A work unit is one sample of 64 rays, one ray per lane (all
+// their samples, in groups of SG, where no per-sample storage is given).  Every
+// lane of a wave runs the same steps (proposal traversal, evaluation
+// traversal, decision) in each iteration of one flat loop, whatever its
+// path length, so waves stay converged.  All random numbers of a sample come
+// from counter-based streams keyed by (seed, ray, sample); a ray's result
+// does not depend on the other rays of the launch.
 #include <math.h>
 
 #include "gf_hit.hpp"
@@ -498,10 +500,10 @@ static __device__ __forceinline__ bool prim_on(const MaskView& M, int orig) {
 }
 
 // the largest tentative distance held (and its slot)
-static __device__ __forceinline__ float latest_point(const LaneMem& lm, int* slot) {
+static __device__ __forceinline__ float latest_point(const LaneMem& lm, int np, int* slot) {
     float best = -INFINITY;
     int ks = 0;
-    for (int k = 0; k < TK; ++k) {
+    for (int k = 0; k < np; ++k) {
         float t = lm.t[k * TR_THREADS];
         if (t > best) {
             best = t;
@@ -528,10 +530,11 @@ static __device__ __forceinline__ bool lod_drop(const PrimF& P, const Seg& sg, f
     return f2 * (tc * tc * v2) > sg.lod2;
 }
 
-// Proposal state of a window: points held and window end (the segment end,
-// or the last point held once the buffer is full).
+// Proposal state of a window: points held, the window's capacity, and the
+// window end (the segment end, or the last point held once the buffer is
+// full, in slot `last`).
 struct Prop {
-    int np;
+    int np, cap, last;
     float tcut;
 };
 
@@ -562,18 +565,16 @@ static __device__ void prop_leaf(const SceneView& S, const MaskView& M, const Ce
         if (unit_float(r.y) >= __expf(-0.5f * C.n2 * dt * dt)) continue;  // thinning to the envelope
         float x = unit_float(r.z);
         if (COUNT) ++wk.tent;
-        int ks;
-        if (pr.np < TK) {
+        if (pr.np < pr.cap) {
             lm.t[pr.np * TR_THREADS] = t;
             lm.xi(pr.np) = x;
             ++pr.np;
-            if (pr.np == TK) pr.tcut = latest_point(lm, &ks);
+            if (pr.np == pr.cap) pr.tcut = latest_point(lm, pr.np, &pr.last);
         } else {
             // full: the new point replaces the latest one
-            latest_point(lm, &ks);
-            lm.t[ks * TR_THREADS] = t;
-            lm.xi(ks) = x;
-            pr.tcut = latest_point(lm, &ks);
+            lm.t[pr.last * TR_THREADS] = t;
+            lm.xi(pr.last) = x;
+            pr.tcut = latest_point(lm, pr.np, &pr.last);
         }
     }
 }
@@ -702,8 +703,22 @@ static __device__ __forceinline__ void begin_segment(const SceneView& S, SegStat
 // free flight ends
 static __device__ __forceinline__ void draw_flight(SegState& st, Rng& g) { st.fs = -__logf(1.0f - g.u()); }
 
+// Capacity of the next window of a segment.  A segment tracked for its
+// first real collision only (delta tracking without a transmittance
+// estimate) uses the points of a window up to that collision and drops the
+// rest, so its windows start at WIN0 points and double up to TK; a segment
+// whose ratio-tracking estimate consumes every point takes TK at once.
+// Windows of any capacity are exact samples (the window ends at one of the
+// process's own points).
+#define WIN0 8
+static __device__ __forceinline__ int window_cap(const SegState& st) {
+    return st.mode == MODE_DELTA ? min(TK, WIN0 << min(st.win, 3)) : TK;
+}
+
 static __device__ __forceinline__ void begin_prop(Prop& pr, const SegState& st) {
     pr.np = 0;
+    pr.cap = window_cap(st);
+    pr.last = 0;
     pr.tcut = st.sg.tb;
 }
 
