@@ -538,14 +538,13 @@ struct Prop {
     float tcut;
 };
 
-// Proposal work of one leaf j: draws its tentative points into lm.t /
+// Proposal work of one primitive P: draws its tentative points into lm.t /
 // lm.xi.  The random numbers of a chord come from its own
 // counter-based stream (segment key; primitive, window, proposal), so the
 // points do not depend on the order in which chords are visited.
 template <bool COUNT>
-static __device__ void prop_leaf(const SceneView& S, const MaskView& M, const CellW& cw, const Seg& sg, uint32_t k0,
-                                 uint32_t k1, int win, int j, Prop& pr, const LaneMem& lm, Work& wk) {
-    PrimF P = load_prim(S.prims, j);
+static __device__ void prop_leaf(const MaskView& M, const CellW& cw, const Seg& sg, uint32_t k0, uint32_t k1, int win,
+                                 const PrimF& P, Prop& pr, const LaneMem& lm, Work& wk) {
     if (COUNT) ++wk.prims;
     float mw = lm.mw(P.cell);
     if (mw == 0.0f || !prim_on(M, P.orig)) return;
@@ -729,40 +728,58 @@ static __device__ void lane_propose(const SceneView& S, const MaskView& M, const
                                     const LaneMem& lm, Work& wk) {
     const Seg& sg = st.sg;
     lane_traverse<COUNT>(S, st.cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, sg.ta, pr.tcut, lm, wk,
-                         [&](int j) { prop_leaf<COUNT>(S, M, st.cw, sg, st.k0, st.k1, st.win, j, pr, lm, wk); });
+                         [&](int j) {
+                             prop_leaf<COUNT>(M, st.cw, sg, st.k0, st.k1, st.win, load_prim(S.prims, j), pr, lm, wk);
+                         });
 }
 
 // Packet traversal for the windows of a whole wave at once (coherent camera
 // rays): the node index, the stack (LDS, pstk) and the leaf are
 // wave-uniform, so node records come through the scalar cache; each lane
 // tests its own ray over its own [ta, tb] (tb re-read at every node) and the
-// wave descends where any lane hits; leaf(j) runs on the lanes whose ray
-// meets the leaf's box.  Children are visited left first, so the leaves a
+// wave descends where any lane hits; leaf(j, record of j) runs on the lanes
+// whose ray meets the leaf's box.  Children are visited left first, so the leaves a
 // lane processes come in tree order whatever the other lanes do.
-template <bool COUNT, class LeafFn>
+template <bool COUNT, bool PF, class LeafFn>
 static __device__ __forceinline__ void packet_walk(const SceneView& S, const SegState& st, bool act, float ta,
                                                    const float& tb, int* __restrict__ pstk, Work& wk, LeafFn&& leaf) {
     const Seg& sg = st.sg;
+    // a leaf's records are wave-uniform scalar loads; the next one is
+    // issued before the current one is processed, so its latency overlaps
+    // that work
     auto leaves = [&](int c) {
         int first, count;
         leaf_range(c, &first, &count);
-        for (int k = 0; k < count; ++k) leaf(first + k);
+        PrimF nx = load_prim(S.prims, first);
+        for (int k = 0; k < count; ++k) {
+            const PrimF P = nx;
+            if (k + 1 < count) nx = load_prim(S.prims, first + k + 1);
+            leaf(first + k, P);
+        }
     };
     if (S.croot < 0) {
         if (act) leaves(S.croot);
         return;
     }
     const float ix = 1.0f / sg.vx, iy = 1.0f / sg.vy, iz = 1.0f / sg.vz;
-    int sp = 0, node = 0;
+    int sp = 0;
+    TNode cur = S.cnodes[0];
     for (;;) {
-        const TNode* nd = S.cnodes + node;
         if (COUNT && act) ++wk.nodes;
-        uint32_t c = nd->cells;
+        const int lc = cur.lchild, rc = cur.rchild;
+        // PF: the internal children's records are loaded before this node's
+        // tests and leaves, so a step down finds them in registers (32 more
+        // scalar registers; only the instance that has them to spare asks)
+        TNode nl, nr;
+        if (PF) {
+            if (lc >= 0) nl = S.cnodes[lc];
+            if (rc >= 0) nr = S.cnodes[rc];
+        }
+        const uint32_t c = cur.cells;
         float tbn = tb;
-        bool hl = act && (c & 0xffffu & st.cw.cells) && slab_hit(nd->lbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, ta, tbn);
-        bool hr = act && ((c >> 16) & st.cw.cells) && slab_hit(nd->rbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, ta, tbn);
+        bool hl = act && (c & 0xffffu & st.cw.cells) && slab_hit(cur.lbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, ta, tbn);
+        bool hr = act && ((c >> 16) & st.cw.cells) && slab_hit(cur.rbox, sg.ox, sg.oy, sg.oz, ix, iy, iz, ta, tbn);
         uint64_t bl = __ballot(hl), br = __ballot(hr);
-        int lc = nd->lchild, rc = nd->rchild;
         if (bl && lc < 0) {
             if (hl) leaves(lc);
             bl = 0;
@@ -774,25 +791,23 @@ static __device__ __forceinline__ void packet_walk(const SceneView& S, const Seg
         if (bl && br) {
             pstk[sp] = rc;
             ++sp;
-            node = lc;
+            cur = PF ? nl : S.cnodes[lc];
         } else if (bl) {
-            node = lc;
+            cur = PF ? nl : S.cnodes[lc];
         } else if (br) {
-            node = rc;
+            cur = PF ? nr : S.cnodes[rc];
         } else {
             if (sp == 0) break;
             --sp;
-            node = pstk[sp];
+            cur = S.cnodes[uniform_int(pstk[sp])];
         }
-        node = uniform_int(node);
     }
 }
 
-// kappa and mu from primitive j at the sorted points of a window in [pa, pb]
+// kappa and mu from primitive P at the sorted points of a window in [pa, pb]
 template <bool COUNT>
-static __device__ __forceinline__ void eval_leaf(const SceneView& S, const MaskView& M, const SegState& st, int j,
-                                                 float pa, float pb, int np, const LaneMem& lm, Work& wk) {
-    PrimF P = load_prim(S.prims, j);
+static __device__ __forceinline__ void eval_leaf(const MaskView& M, const SegState& st, const PrimF& P, float pa,
+                                                 float pb, int np, const LaneMem& lm, Work& wk) {
     if (COUNT) ++wk.prims;
     float mw = lm.mw(P.cell);
     if (mw == 0.0f || !prim_on(M, P.orig)) return;
@@ -1092,9 +1107,8 @@ gf_status gf_ensure_weideman_track() {
 // Weighted optical depth of primitive j's chord over [lo, hi], added to the
 // TK bins of width (hi - lo) / TK piece by piece.
 template <bool COUNT>
-static __device__ void bin_chord(const SceneView& S, const MaskView& M, const SegState& st, int j, float lo,
-                                 float hi, const LaneMem& lm, Work& wk) {
-    PrimF P = load_prim(S.prims, j);
+static __device__ void bin_chord(const SceneView& S, const MaskView& M, const SegState& st, int j, const PrimF& P,
+                                 float lo, float hi, const LaneMem& lm, Work& wk) {
     if (COUNT) ++wk.prims;
     const float w = lm.w(P.cell);
     if (w == 0.0f || !prim_on(M, P.orig)) return;
@@ -1130,12 +1144,13 @@ static __device__ void bin_pass(const SceneView& S, const MaskView& M, const Seg
                                 float hi, const LaneMem& lm, int* pstk, Work& wk) {
     if (act)
         for (int b = 0; b < TK; ++b) lm.t[b * TR_THREADS] = 0.0f;
-    auto leaf = [&](int j) { bin_chord<COUNT>(S, M, st, j, lo, hi, lm, wk); };
+    auto leaf = [&](int j, const PrimF& P) { bin_chord<COUNT>(S, M, st, j, P, lo, hi, lm, wk); };
     if (PACKET) {
-        packet_walk<COUNT>(S, st, act, lo, hi, pstk, wk, leaf);
+        packet_walk<COUNT, false>(S, st, act, lo, hi, pstk, wk, leaf);
     } else if (act) {
         const Seg& sg = st.sg;
-        lane_traverse<COUNT>(S, st.cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, lo, hi, lm, wk, leaf);
+        lane_traverse<COUNT>(S, st.cw.cells, sg.ox, sg.oy, sg.oz, sg.vx, sg.vy, sg.vz, lo, hi, lm, wk,
+                             [&](int j) { leaf(j, load_prim(S.prims, j)); });
     }
 }
 
@@ -1274,8 +1289,7 @@ static __device__ void exact_T_packet(const SceneView& S, const MaskView& M, Seg
                                       int* pstk, Work& wk) {
     act = act && st.live;
     float acc = 0.0f;
-    packet_walk<COUNT>(S, st, act, st.sg.ta, st.sg.tb, pstk, wk, [&](int j) {
-        PrimF P = load_prim(S.prims, j);
+    packet_walk<COUNT, true>(S, st, act, st.sg.ta, st.sg.tb, pstk, wk, [&](int, const PrimF& P) {
         if (COUNT) ++wk.prims;
         const float w = lm.w(P.cell);
         if (w == 0.0f || !prim_on(M, P.orig)) return;
@@ -1292,21 +1306,21 @@ static __device__ void exact_T_packet(const SceneView& S, const MaskView& M, Seg
 
 // Camera segments of a whole wave, window by window: packet proposal and
 // packet evaluation passes; a lane whose segment is finished sits out.
-template <bool COUNT>
+template <bool COUNT, bool PF>
 static __device__ void track_camera(const SceneView& S, const MaskView& M, SegState& st, bool valid,
                                     const LaneMem& lm, int* pstk, Work& wk) {
     bool open = valid && st.live;
     while (__any(open)) {
         Prop pr;
         begin_prop(pr, st);
-        packet_walk<COUNT>(S, st, open, st.sg.ta, pr.tcut, pstk, wk, [&](int j) {
-            prop_leaf<COUNT>(S, M, st.cw, st.sg, st.k0, st.k1, st.win, j, pr, lm, wk);
+        packet_walk<COUNT, PF>(S, st, open, st.sg.ta, pr.tcut, pstk, wk, [&](int, const PrimF& P) {
+            prop_leaf<COUNT>(M, st.cw, st.sg, st.k0, st.k1, st.win, P, pr, lm, wk);
         });
         const bool ev = open && pr.np > 0;
         if (ev) open_points(lm, pr.np);
         const float pa = ev ? lm.t[0] : 0.0f, pb = ev ? lm.t[(pr.np - 1) * TR_THREADS] : -1.0f;
-        packet_walk<COUNT>(S, st, ev, pa, pb, pstk, wk,
-                           [&](int j) { eval_leaf<COUNT>(S, M, st, j, pa, pb, pr.np, lm, wk); });
+        packet_walk<COUNT, PF>(S, st, ev, pa, pb, pstk, wk,
+                           [&](int, const PrimF& P) { eval_leaf<COUNT>(M, st, P, pa, pb, pr.np, lm, wk); });
         if (open && decide_window<COUNT>(S, M, st, pr, lm, wk)) open = false;
     }
 }
@@ -1487,7 +1501,7 @@ static __device__ void render_rays(const SceneView& S, const MaskView& M, const 
             if (EXACT)
                 exact_segment<COUNT, true>(S, M, rl.st, valid, lm, pstk, wk);
             else
-                track_camera<COUNT>(S, M, rl.st, valid, lm, pstk, wk);
+                track_camera<COUNT, FF == 1>(S, M, rl.st, valid, lm, pstk, wk);
             if (valid) {
                 rl.camera_done(A);
                 lm.ctc(k) = rl.st.tc;
@@ -1549,7 +1563,7 @@ static __device__ void ratio_rays(const SceneView& S, const MaskView& M, const f
             g.init(seed, (uint32_t)idx, (uint32_t)s, 1u);
             begin_segment(S, st, r, r + 3, r[6], r[7], fixed_weights(M.cells, lm.cw), MODE_RATIO, M.lod2, g);
         }
-        track_camera<COUNT>(S, M, st, valid, lm, pstk, wk);
+        track_camera<COUNT, false>(S, M, st, valid, lm, pstk, wk);
         s1 += st.T;
         s2 += st.T * st.T;
     }
