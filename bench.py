@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--serving-sweep", action="store_true", help="serving at 0.35, 0.7, 1.0, 1.4 x saturation")
+    ap.add_argument("--serving-loads", default="",
+                    help="comma-separated loads (multiples of the plain renderer's saturation rate) to serve at")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for hardware byte counters)")
     ap.add_argument("--bin", default="mixture", help="orientation-bin strategy of the multiple-scattering workload")
@@ -86,10 +88,6 @@ def main():
     from gen import workloads as W
 
     torch.cuda.init()
-    if args.workload.startswith("blob1m"):
-        return multiple_scattering_bench(args)
-    if args.ratio_shadow:
-        KERNELS["render"] = "void k_render<false, 0>"
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
@@ -97,6 +95,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload.startswith("blob1m"):
+        return multiple_scattering_bench(args)
+    if args.ratio_shadow:
+        KERNELS["render"] = "void k_render<false, 0>"
     name = args.workload
     params_h, rays_h, rho = W.scene(name), W.rays(name), W.rho(name)
     width = int(math.isqrt(rays_h.shape[0]))
@@ -460,7 +462,10 @@ def serving(args, gf, W, np, torch):
     def done(tag):
         return lambda k, t: log("serving (%s): request %d done at %.1f s" % (tag, k, t))
 
-    for f in ([0.35, 0.7, 1.0, 1.4] if args.serving_sweep else [0.7]):
+    loads = [0.35, 0.7, 1.0, 1.4] if args.serving_sweep else [0.7]
+    if args.serving_loads:
+        loads = [float(x) for x in args.serving_loads.split(",")]
+    for f in loads:
         qps = f * plain_rate
         arrivals = gen.poisson_arrivals(n, qps, seed=6)
         log("serving: %.2f x saturation = %.3f requests/s, %d requests" % (f, qps, n))
