@@ -24,6 +24,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -264,12 +265,14 @@ def work_per_sample(counts, k, samples):
     return {n: round(v / samples, 2) for n, v in zip(names, c)}
 
 
-def profile_figures(workload, kernel):
+def profile_figures(workload, kernel, rows=0):
     """Per-launch figures of the dominant kernel from the committed rocprofv3
     summaries, used only while their recorded source hash matches the HIP
-    sources: measured HBM bytes (profiles/<kernel>_<workload>_pmc.txt,
-    FETCH_SIZE and WRITE_SIZE scaled by the calibration factors recorded
-    there) and VALU instructions (profiles/<kernel>_<workload>_sq.txt)."""
+    sources and their command rendered the same rows (rows > 0: `--rows
+    rows`; 0: the full frame): measured HBM bytes
+    (profiles/<kernel>_<workload>_pmc.txt, FETCH_SIZE and WRITE_SIZE scaled
+    by the calibration factors recorded there) and VALU instructions
+    (profiles/<kernel>_<workload>_sq.txt)."""
     sys.path.insert(0, ROOT)
     import profile_summary
     out = {}
@@ -280,6 +283,10 @@ def profile_figures(workload, kernel):
             continue
         text = open(path).read().splitlines()
         if not any(l.startswith("# source hash: %s" % profile_summary.source_hash()) for l in text):
+            continue
+        cmds = [l for l in text if l.startswith("# command") or l.startswith("# fetch command")]
+        m = re.search(r"--rows (\d+)", cmds[0]) if cmds else None
+        if (int(m.group(1)) if m else 0) != rows:
             continue
         header = next((l for l in text if l.startswith("kernel ")), None)
         for line in text:
@@ -364,7 +371,7 @@ def multiple_scattering_bench(args):
     band_samples = band.shape[0]
     alg_frame = npix * (RAY_BYTES + OUT_BYTES) + (NODE_BYTES * c[5] + PRIM_BYTES * c[6]) * (npix * spp / band_samples)
     ach = alg_frame / (ren_ms * 1e-3) / 1e9
-    prof = profile_figures(name, "render")
+    prof = profile_figures(name, "render", rows if rows != width else 0)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": prof.get("traffic"), "kernel": KERNELS["render"],
                 "algorithmic_bytes_per_launch": int(alg_frame), "launch_ms": round(ren_ms, 3),
