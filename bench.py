@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=12)
     ap.add_argument("--serving-sweep", action="store_true", help="serving at 0.35, 0.7, 1.0, 1.4 x saturation")
+    ap.add_argument("--serving-max-tiles", type=int, default=192, help="tiles of 4096 rays per serving batch")
     ap.add_argument("--serving-loads", default="",
                     help="comma-separated loads (multiples of the plain renderer's saturation rate) to serve at")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -463,7 +464,7 @@ def serving(args, gf, W, np, torch):
     k = min(4, n)
     serve.run_plain(scenes, reqs[:k], np.zeros(k))
     plain_rate = k / (time.perf_counter() - t0)
-    out = {"requests": n, "scenes": W.SERVE_SCENES, "mem_budget": budget,
+    out = {"requests": n, "scenes": W.SERVE_SCENES, "mem_budget": budget, "max_tiles": args.serving_max_tiles,
            "plain_saturation_qps": round(plain_rate, 4), "points": []}
 
     def done(tag):
@@ -477,7 +478,8 @@ def serving(args, gf, W, np, torch):
         arrivals = gen.poisson_arrivals(n, qps, seed=6)
         log("serving: %.2f x saturation = %.3f requests/s, %d requests" % (f, qps, n))
         lat_s, mk_s, _, held = serve.run_server(scenes, reqs, arrivals, mem_budget=budget, tile_rays=4096,
-                                                max_tiles=192, time_limit=1800, on_done=done("batching"))
+                                                max_tiles=args.serving_max_tiles, time_limit=1800,
+                                                on_done=done("batching"))
         lat_p, mk_p, _ = serve.run_plain(scenes, reqs, arrivals, time_limit=1800, on_done=done("plain"))
         out["points"].append({"load": f, "qps": round(qps, 4),
                               "continuous_batching": serve.summarize(lat_s, mk_s, reqs),
