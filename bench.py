@@ -34,10 +34,10 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 # VALU issue peak: 256 CUs x one wave64 instruction per cycle (4 SIMD16 units,
 # 4 cycles each) x 2.4 GHz; 64 lanes x 2 (FMA) x 614.4e9 = 78.6 TFLOP/s, the
-# float32 peak without packed instructions (which this build turns off)
+# float32 peak without packed instructions (the library is compiled without them)
 PEAK_VALU_INSTS = 256 * 2.4e9
-# bytes each unit of work must touch (the per-unit figures of the hot-path
-# table): optical depth per ray 32 (ray) + 8 (tau, T) + 60 per primitive with
+# bytes each unit of work must touch (the per-unit byte model of the
+# measurement): optical depth per ray 32 (ray) + 8 (tau, T) + 60 per primitive with
 # a non-empty chord + 32 per box met (half a 64 B node record); tracking per
 # consumed tentative point 32 per node a point query visits + 60 per
 # primitive whose support contains the point, plus 40 per camera ray
